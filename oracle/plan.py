@@ -1,0 +1,103 @@
+"""Independent implementation of the written integer plan rules (test infrastructure).
+
+The HIP library's planner must produce exactly these integers.  Rules:
+
+P1  Effective order: De = largest d with R_d > 0 (De = 2 if every rank is 0).
+P2  FFT length: L = max(16, smallest power of two >= De*N - 1).  A cyclic
+    length L keeps every gain output k in [2, N] free of wrap-around for every
+    d <= De, because k + L > d*N for k >= 2.  M = L/2 is the complex length of
+    the half-length transform that carries a real length-L transform.
+P3  Column ids: scan d = 2..D ascending, m = 1..d, r = 1..R_d; the column
+    U^(d)_m(:, r) gets the id of the first earlier column that is bitwise equal
+    (all N binary64 words), else the next new id.  u = number of ids.
+P4  Gain terms: for each (d, r) the key is the ascending-sorted tuple of the d
+    column ids; equal keys merge and count a multiplicity.  Order: by d, then
+    lexicographic key.  Coefficient = multiplicity / d!.
+P5  Loss terms: for each (d, r) the key is (d, id of mode d, ascending-sorted ids
+    of modes 1..d-1); equal keys merge with multiplicity.  Order: by that key.
+    Coefficient = multiplicity / (d-1)!.
+P6  Two-pass split: lg = log2 M; M1 = 2^ceil(lg/2), M2 = M/M1.  With cs = 16
+    bytes per stored complex (fp64, fp32c) or 8 (fp32): while u*2*M2*cs > 64 KiB
+    and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048 or
+    u*2*M2*cs > 144 KiB.
+P7  Column tile: g = min(M2, max(1, 2048 / M1)) adjacent columns per workgroup.
+
+Flat table (int64), as exported for comparison:
+    [L, M1, M2, g, u, Tp, Tq, De,
+     colmap in scan order (one id per (d, m, r)),
+     per gain term:  d, multiplicity, ids[d],
+     per loss term:  d, multiplicity, kmode id, ids[d-1]]
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PREC_BYTES = {"fp64": 16, "fp32": 8, "fp32c": 16}
+
+
+class Unsupported(ValueError):
+    pass
+
+
+def _log2_exact(x: int) -> int:
+    assert x > 0 and (x & (x - 1)) == 0
+    return x.bit_length() - 1
+
+
+def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64"):
+    ranks = {d: (kernel[d].shape[1] if d in kernel else 0) for d in range(2, D + 1)}
+    De = max([d for d in range(2, D + 1) if ranks[d] > 0], default=2)
+    L = 1
+    while L < De * N - 1:
+        L *= 2
+    L = max(16, L)
+    M = L // 2
+
+    ids = []          # list of bytes for each distinct column
+    colmap = []
+    cmap = {}
+    for d in range(2, D + 1):
+        for m in range(d):
+            for r in range(ranks[d]):
+                key = np.ascontiguousarray(kernel[d][m, r], dtype=np.float64).tobytes()
+                found = -1
+                for j, kk in enumerate(ids):
+                    if kk == key:
+                        found = j
+                        break
+                if found < 0:
+                    ids.append(key)
+                    found = len(ids) - 1
+                colmap.append(found)
+                cmap[(d, m, r)] = found
+    u = len(ids)
+
+    pt = {}
+    qt = {}
+    for d in range(2, D + 1):
+        for r in range(ranks[d]):
+            pk = tuple(sorted(cmap[(d, m, r)] for m in range(d)))
+            pt[pk] = pt.get(pk, 0) + 1
+            qk = (d, cmap[(d, d - 1, r)], tuple(sorted(cmap[(d, m, r)] for m in range(d - 1))))
+            qt[qk] = qt.get(qk, 0) + 1
+    pterms = sorted(pt.items(), key=lambda kv: (len(kv[0]), kv[0]))
+    qterms = sorted(qt.items(), key=lambda kv: kv[0])
+
+    cs = PREC_BYTES[prec]
+    lg = _log2_exact(M)
+    M1 = 1 << ((lg + 1) // 2)
+    M2 = M // M1
+    while u * 2 * M2 * cs > 65536 and M1 < 2048:
+        M1 *= 2
+        M2 //= 2
+    if M1 > 2048 or u * 2 * M2 * cs > 147456:
+        raise Unsupported(f"no two-pass split for L={L} with u={u} columns")
+    g = min(M2, max(1, 2048 // M1))
+
+    flat = [L, M1, M2, g, u, len(pterms), len(qterms), De] + colmap
+    for key, mult in pterms:
+        flat += [len(key), mult] + list(key)
+    for (d, km, others), mult in qterms:
+        flat += [d, mult, km] + list(others)
+    return dict(L=L, M=M, M1=M1, M2=M2, g=g, u=u, De=De, colmap=colmap,
+                pterms=pterms, qterms=qterms, flat=np.array(flat, dtype=np.int64))

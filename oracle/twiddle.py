@@ -1,0 +1,18 @@
+"""Reference roots of unity w_P^e = exp(-2 pi i e / P), correctly rounded to
+binary64 with mpmath at 60 significant digits.  Test infrastructure only."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def twiddles_ref(P: int, idx=None):
+    import mpmath
+    mpmath.mp.dps = 60
+    if idx is None:
+        idx = range(P)
+    out = np.empty((len(idx), 2), dtype=np.float64)
+    for j, e in enumerate(idx):
+        a = -2 * mpmath.pi * e / P
+        out[j, 0] = float(mpmath.cos(a))
+        out[j, 1] = float(mpmath.sin(a))
+    return out
