@@ -1,0 +1,167 @@
+/*
+ * agg.h - C ABI of libagg: the right-hand side of the multi-particle
+ * aggregation (Smoluchowski-type) system with kernels in canonical polyadic
+ * (CP) form, and its explicit second-order Runge-Kutta (Heun) integration, on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The system (Sec. 1 of Stefonishin, Matveev, Zheltkov, "Tensors in modelling
+ * multi-particle interactions"), truncated to sizes k = 1..N:
+ *
+ *   dn_k/dt = sum_{d=2..D} ( p_k^(d) + q_k^(d) )
+ *   p_k^(d) =  1/d!      * sum_{i in [1,N]^d, i_1+..+i_d = k} C^(d)_i n_{i_1}..n_{i_d}
+ *   q_k^(d) = -n_k/(d-1)! * sum_{i in [1,N]^(d-1)} C^(d)_{i,k} n_{i_1}..n_{i_{d-1}}
+ *
+ * with every kernel tensor given by CP factors (Sec. 1, CP remark):
+ *   C^(d)_{i_1..i_d} = sum_{r=1..R_d} prod_{m=1..d} U^(d)_m(i_m, r).
+ * The size index k of the loss term sits in the LAST mode (m = d).  Mass that
+ * would grow past size N is dropped (no sink class).
+ *
+ * Conventions shared by every entry point:
+ *   - A state vector is binary64, n[k-1] = n_k; a batch is B such vectors back to
+ *     back (B*N doubles).  State pointers are DEVICE pointers.
+ *   - Calls that take a plan are stream-ordered and asynchronous on the plan's
+ *     HIP stream, like HIP API calls: the caller synchronises that stream before
+ *     reading results on the host.  A plan is not thread-safe.
+ *   - The spectral path (FFT convolutions) runs in the plan's precision; the state,
+ *     the loss-term dot products, the Heun update and all moments are binary64.
+ *   - No exception crosses the ABI; every call returns an agg_status and, on
+ *     error, sets a thread-local message readable with agg_last_error().
+ */
+#ifndef AGG_H
+#define AGG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AGG_MAX_D 8
+
+typedef int32_t agg_status;
+enum {
+  AGG_OK = 0,
+  AGG_PENDING = 1,        /* agg_poll: the request has not finished yet          */
+  AGG_EINVAL = -1,        /* an argument is out of its documented range         */
+  AGG_ENOMEM = -2,        /* device/host allocation failed or budget exceeded   */
+  AGG_EHIP = -3,          /* a HIP runtime call failed                          */
+  AGG_ENONFINITE = -4,    /* non-finite factor, initial value or final state    */
+  AGG_ENOTFOUND = -5,     /* unknown ticket                                     */
+  AGG_ECANCELLED = -6,    /* request cancelled (engine destroyed)               */
+  AGG_EUNSUPPORTED = -7   /* valid but beyond this build's limits (size, u)     */
+};
+
+/* Arithmetic of the spectral path.  AGG_FP32C carries float-float (hi+lo)
+ * pairs through every FFT pass, twiddle and product (error-free transforms). */
+typedef enum { AGG_FP64 = 0, AGG_FP32 = 1, AGG_FP32C = 2 } agg_precision;
+
+/* One collision order d: C^(d) = sum_r prod_m U_m(i_m, r).
+ * U[m-1] is a HOST pointer to N*rank doubles, column-major by rank:
+ * U[m-1][r*N + (i-1)] = U^(d)_m(i, r), for m = 1..d.  Mode m = d is the k-mode.
+ * rank = 0 means the order is absent.  Entries U[d..AGG_MAX_D-1] are ignored. */
+typedef struct {
+  int32_t d;
+  int32_t rank;
+  const double* U[AGG_MAX_D];
+} agg_term;
+
+typedef struct agg_plan agg_plan;
+
+/* Build a plan for `batch` independent states that share one kernel set.
+ * Terms: 2 <= d <= D, each d at most once, any order; orders not listed are
+ * absent.  The factors are copied (deduplicated by bitwise column equality)
+ * into plan-owned device memory: the caller may free them on return.
+ * hip_stream: a hipStream_t (NULL = the null stream) on which every later call
+ * of this plan is enqueued.
+ * Errors: AGG_EINVAL (D outside [2, AGG_MAX_D], N < 1, bad/duplicate d, rank < 0,
+ * NULL factor with rank > 0, batch < 1, unknown precision, out == NULL),
+ * AGG_ENONFINITE (a non-finite factor), AGG_EUNSUPPORTED (transform length
+ * above 2^23, or too many distinct columns for the two-pass transform),
+ * AGG_ENOMEM, AGG_EHIP. */
+agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
+                           agg_precision prec, int32_t batch, void* hip_stream,
+                           agg_plan** out);
+agg_status agg_plan_destroy(agg_plan* plan);
+
+/* dndt = f(n) for each of the batch states (Sec. 1, the full right-hand side).
+ * n, dndt: device, batch*N doubles each, must not overlap.  Asynchronous. */
+agg_status agg_rhs(agg_plan* plan, const double* n, double* dndt);
+
+/* One Heun step in place (Sec. 3: explicit second-order Runge-Kutta, two
+ * right-hand-side evaluations): k1 = f(n), n~ = n + dt k1, k2 = f(n~),
+ * n <- n + dt/2 (k1 + k2).  n: device, batch*N.  dt > 0 and finite.  Async. */
+agg_status agg_rk2_step(agg_plan* plan, double* n, double dt);
+
+typedef struct {
+  int64_t steps;        /* Heun steps taken                                     */
+  int64_t rhs_evals;    /* right-hand-side evaluations (2 per step, per state)  */
+  double t_final;       /* time reached                                         */
+  double m0_initial, m1_initial;   /* sum n_k and sum k n_k over the batch, t=0 */
+  double m0_final, m1_final;       /* the same at t_final                       */
+  int64_t nonfinite;    /* count of non-finite entries of the final state       */
+} agg_solve_stats;
+
+/* Integrate n from t = 0 to t_end with step dt in place.  Time grid: the step
+ * count is round(t_end/dt) when t_end/dt is within 1e-9 (relative) of an
+ * integer, else ceil(t_end/dt) with the last step shortened to reach t_end;
+ * t_end = 0 takes no step.  With st == NULL the call is asynchronous.  With st
+ * non-NULL it synchronises the stream, fills st (binary64 moments) and returns
+ * AGG_ENONFINITE if the final state holds a non-finite value (state still
+ * written).  Errors: AGG_EINVAL for dt <= 0, t_end < 0, or non-finite. */
+agg_status agg_solve(agg_plan* plan, double* n, double dt, double t_end, agg_solve_stats* st);
+
+/* ---- introspection (host only: no device is touched) ----------------------
+ * agg_plan_tables writes the plan's integer tables as int64 (layout:
+ * [L, M1, M2, g, u, Tp, Tq, De, column id per (d, m, r) in scan order d, m, r,
+ *  per gain term: d, multiplicity, ids[d],
+ *  per loss term: d, multiplicity, k-mode id, ids[d-1]])
+ * into out[0..cap) and its full length into *len.  AGG_EINVAL if cap is short
+ * (len still set).  agg_twiddles writes exp(-2 pi i e / P) for e = 0..P-1 as
+ * interleaved binary64 (re, im) pairs into out[0..2P) (P a power of two). */
+agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
+                           agg_precision prec, int64_t* out, int64_t cap, int64_t* len);
+agg_status agg_twiddles(int64_t P, double* out);
+
+/* ---- serving: continuous batching of whole solves ------------------------- */
+typedef struct {
+  int32_t device;          /* HIP device ordinal                                 */
+  int64_t mem_budget;      /* device bytes the engine may hold (0 = 8 GiB)       */
+  int32_t max_slots;       /* concurrent solves on the device (0 = 256)          */
+} agg_engine_config;
+
+typedef struct {
+  double t_submit, t_admit, t_finish;  /* seconds on the engine's steady clock  */
+  int64_t steps;
+  int32_t status;                      /* final agg_status of the solve          */
+} agg_request_stats;
+
+typedef struct agg_engine agg_engine;
+
+agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out);
+/* Cancels pending and running requests; their tickets end AGG_ECANCELLED. */
+agg_status agg_engine_destroy(agg_engine* e);
+
+/* Queue one solve n(0) = n0 -> n(t_end) (same time grid as agg_solve).  Host
+ * pointers; factors and n0 are copied before return.  Never blocks on the GPU.
+ * Errors as agg_plan_create/agg_solve, plus AGG_ENOMEM when the request's
+ * device footprint alone exceeds the engine budget. */
+agg_status agg_submit(agg_engine* e, int32_t D, int64_t N, const agg_term* terms,
+                      int32_t nterms, const double* n0, double dt, double t_end,
+                      agg_precision prec, uint64_t* ticket);
+
+/* Non-blocking.  AGG_PENDING until done; then writes n_out (host, N doubles)
+ * and st (nullable), forgets the ticket, and returns the solve's status
+ * (AGG_OK, AGG_ENONFINITE, ...).  AGG_ENOTFOUND for an unknown ticket. */
+agg_status agg_poll(agg_engine* e, uint64_t ticket, double* n_out, agg_request_stats* st);
+
+/* Engine-wide counters: completed solves, in-flight slots, queued requests,
+ * device bytes in use. */
+agg_status agg_engine_counters(agg_engine* e, int64_t* completed, int64_t* running,
+                               int64_t* queued, int64_t* bytes_in_use);
+
+const char* agg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AGG_H */

@@ -1,5 +1,5 @@
 """Reference roots of unity w_P^e = exp(-2 pi i e / P), correctly rounded to
-binary64 with mpmath at 60 significant digits.  Test infrastructure only."""
+binary64 with mpmath's cospi/sinpi at 60 significant digits.  Test infrastructure only."""
 from __future__ import annotations
 
 import numpy as np
@@ -12,7 +12,7 @@ def twiddles_ref(P: int, idx=None):
         idx = range(P)
     out = np.empty((len(idx), 2), dtype=np.float64)
     for j, e in enumerate(idx):
-        a = -2 * mpmath.pi * e / P
-        out[j, 0] = float(mpmath.cos(a))
-        out[j, 1] = float(mpmath.sin(a))
+        a = mpmath.mpf(-2 * int(e)) / P        # exact: P is a power of two
+        out[j, 0] = float(mpmath.cospi(a))     # cos(pi a), exact zeros at multiples of 1/2
+        out[j, 1] = float(mpmath.sinpi(a))
     return out

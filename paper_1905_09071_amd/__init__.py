@@ -1,0 +1,161 @@
+"""Python binding of libagg (include/agg.h): argument marshalling only.
+
+Every step of the right-hand side and of the time stepping runs in the HIP
+kernels of libagg.so; torch provides device memory (float64 tensors) and
+streams.  Kernel factors are numpy arrays of shape (d, R_d, N) with
+U[m-1, r, i-1] = U^(d)_m(i, r); mode d carries k in the loss term.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (AGG_EINVAL, AGG_ENOMEM, AGG_ENONFINITE, AGG_ENOTFOUND, AGG_EUNSUPPORTED,  # noqa: F401
+                   AGG_OK, AGG_PENDING, AGG_MAX_D, PREC, AggError, agg_engine_config,
+                   agg_request_stats, agg_solve_stats, agg_term, check, lib)
+
+__all__ = ["Plan", "Engine", "plan_tables", "twiddles", "AggError", "PREC", "make_terms"]
+
+
+def make_terms(D: int, N: int, kernel: dict):
+    """Build the agg_term array; returns (array, keepalive list)."""
+    items = sorted(kernel.items())
+    arr = (agg_term * max(len(items), 1))()
+    keep = []
+    for t, (d, U) in enumerate(items):
+        U = np.asarray(U, dtype=np.float64)
+        if U.ndim != 3 or U.shape[0] != d or U.shape[2] != N:
+            raise ValueError(f"factors of order {d} must have shape (d, R, N) = ({d}, R, {N})")
+        arr[t].d = d
+        arr[t].rank = U.shape[1]
+        for m in range(d):
+            col = np.ascontiguousarray(U[m])
+            keep.append(col)
+            arr[t].U[m] = col.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return arr, len(items), keep
+
+
+def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64") -> np.ndarray:
+    """The planner's integer tables (host only, no device touched)."""
+    terms, nt, keep = make_terms(D, N, kernel)
+    ln = ctypes.c_int64(0)
+    lib().agg_plan_tables(D, N, terms, nt, PREC[prec], None, 0, ctypes.byref(ln))
+    out = np.zeros(max(ln.value, 1), dtype=np.int64)
+    check(lib().agg_plan_tables(D, N, terms, nt, PREC[prec],
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.size, ctypes.byref(ln)))
+    del keep
+    return out[:ln.value]
+
+
+def twiddles(P: int) -> np.ndarray:
+    out = np.zeros(2 * P)
+    check(lib().agg_twiddles(P, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(P, 2)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_state(t, numel):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("state tensors must be float64 CUDA (HIP) tensors")
+    if not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"state tensor must be contiguous with {numel} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """agg_plan: a kernel set, precision and batch size bound to a stream."""
+
+    def __init__(self, D: int, N: int, kernel: dict, prec: str = "fp64", batch: int = 1, stream=None):
+        self.D, self.N, self.batch, self.prec = D, N, batch, prec
+        terms, nt, keep = make_terms(D, N, kernel)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        check(lib().agg_plan_create(D, N, terms, nt, PREC[prec], batch, _stream_handle(stream),
+                                    ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().agg_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rhs(self, n, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(n)
+        check(lib().agg_rhs(self._h, _check_state(n, self.batch * self.N), _check_state(out, self.batch * self.N)))
+        return out
+
+    def rk2_step(self, n, dt: float):
+        check(lib().agg_rk2_step(self._h, _check_state(n, self.batch * self.N), float(dt)))
+        return n
+
+    def solve(self, n, dt: float, t_end: float, stats: bool = True):
+        st = agg_solve_stats()
+        rc = lib().agg_solve(self._h, _check_state(n, self.batch * self.N), float(dt), float(t_end),
+                             ctypes.byref(st) if stats else None)
+        check(rc)
+        return st if stats else None
+
+
+class Engine:
+    """agg_engine: continuous-batching solve service on one device."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0, max_slots: int = 0):
+        cfg = agg_engine_config(device, mem_budget, max_slots)
+        h = ctypes.c_void_p()
+        check(lib().agg_engine_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().agg_engine_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, D, N, kernel, n0, dt, t_end, prec="fp32c") -> int:
+        terms, nt, keep = make_terms(D, N, kernel)
+        n0 = np.ascontiguousarray(n0, dtype=np.float64)
+        if n0.size != N:
+            raise ValueError("n0 must have N entries")
+        t = ctypes.c_uint64(0)
+        check(lib().agg_submit(self._h, D, N, terms, nt, n0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               float(dt), float(t_end), PREC[prec], ctypes.byref(t)))
+        del keep
+        return t.value
+
+    def poll(self, ticket: int, N: int):
+        """(status, n_out or None, stats).  status AGG_PENDING while running."""
+        out = np.zeros(N)
+        st = agg_request_stats()
+        rc = lib().agg_poll(self._h, ticket, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
+        if rc == AGG_PENDING:
+            return rc, None, None
+        if rc == AGG_ENOTFOUND:
+            check(rc)
+        return rc, out, st
+
+    def counters(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(lib().agg_engine_counters(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(completed=v[0].value, running=v[1].value, queued=v[2].value, bytes_in_use=v[3].value)

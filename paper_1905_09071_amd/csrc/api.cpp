@@ -1,0 +1,359 @@
+// C ABI of libagg (declared in include/agg.h): plans, the RHS, Heun steps and
+// whole solves on one GPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/agg.h"
+#include "internal.h"
+#include "kernels.h"
+#include "planner.h"
+
+namespace agg {
+
+static thread_local std::string g_err;
+
+agg_status set_error(agg_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+agg_status hip_fail(hipError_t e, const char* what) {
+  return set_error(AGG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Twiddle tables of a transform length in a precision's storage format.
+static std::vector<unsigned char> twiddle_bytes(int prec, const std::vector<double>& w) {
+  size_t n = w.size() / 2;
+  std::vector<unsigned char> out;
+  if (prec == AGG_FP64) {
+    out.resize(n * 16);
+    std::memcpy(out.data(), w.data(), n * 16);
+  } else if (prec == AGG_FP32) {
+    out.resize(n * 8);
+    float* f = (float*)out.data();
+    for (size_t i = 0; i < 2 * n; ++i) f[i] = (float)w[i];
+  } else {
+    out.resize(n * 16);
+    float* f = (float*)out.data();
+    for (size_t i = 0; i < n; ++i) {
+      for (int part = 0; part < 2; ++part) {
+        double x = w[2 * i + part];
+        float hi = (float)x;
+        float lo = (float)(x - (double)hi);
+        f[4 * i + 2 * part] = hi;
+        f[4 * i + 2 * part + 1] = lo;
+      }
+    }
+  }
+  return out;
+}
+
+agg_status DeviceArena::alloc(size_t bytes, void** p) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(AGG_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  ptrs.push_back(*p);
+  total += bytes;
+  return AGG_OK;
+}
+
+void DeviceArena::release() {
+  for (void* p : ptrs) (void)hipFree(p);
+  ptrs.clear();
+  total = 0;
+}
+
+agg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return AGG_OK;
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(s);   // the host vectors are freed on return
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return AGG_OK;
+}
+
+static double factorial(int d) {
+  double f = 1.0;
+  for (int i = 2; i <= d; ++i) f *= (double)i;
+  return f;
+}
+
+agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st) {
+  agg_status rc;
+  st->tab = &T;
+  const int64_t N = T.N;
+  // distinct columns
+  std::vector<double> cols((size_t)T.u * N);
+  for (int c = 0; c < T.u; ++c) std::memcpy(&cols[(size_t)c * N], T.ucols[c].data(), sizeof(double) * N);
+  if ((rc = arena.alloc(cols.size() * 8, (void**)&st->cols))) return rc;
+  if ((rc = upload(st->cols, cols.data(), cols.size() * 8, s))) return rc;
+
+  // term tables
+  std::vector<int> p_off{0}, p_ids, q_off{0}, q_ids, q_km;
+  std::vector<double> p_coef, q_coef;
+  for (size_t t = 0; t < T.p_ids.size(); ++t) {
+    for (int id : T.p_ids[t]) p_ids.push_back(id);
+    p_off.push_back((int)p_ids.size());
+    p_coef.push_back((double)T.p_mult[t] / factorial((int)T.p_ids[t].size()));
+  }
+  for (size_t t = 0; t < T.q_ids.size(); ++t) {
+    for (int id : T.q_ids[t]) q_ids.push_back(id);
+    q_off.push_back((int)q_ids.size());
+    q_km.push_back(T.q_kmode[t]);
+    q_coef.push_back((double)T.q_mult[t] / factorial(T.q_d[t] - 1));
+  }
+  std::vector<unsigned char> ints;
+  auto put = [&](const std::vector<int>& v) {
+    size_t off = ints.size();
+    ints.resize(off + std::max<size_t>(v.size(), 1) * 4);
+    if (!v.empty()) std::memcpy(&ints[off], v.data(), v.size() * 4);
+    return off;
+  };
+  size_t o_poff = put(p_off), o_pids = put(p_ids), o_qoff = put(q_off), o_qids = put(q_ids),
+         o_qkm = put(q_km);
+  void* dints;
+  if ((rc = arena.alloc(ints.size(), &dints))) return rc;
+  if ((rc = upload(dints, ints.data(), ints.size(), s))) return rc;
+  st->p_off = (const int*)((char*)dints + o_poff);
+  st->p_ids = (const int*)((char*)dints + o_pids);
+  st->q_off = (const int*)((char*)dints + o_qoff);
+  st->q_ids = (const int*)((char*)dints + o_qids);
+  st->q_kmode = (const int*)((char*)dints + o_qkm);
+  std::vector<double> coefs(p_coef);
+  coefs.insert(coefs.end(), q_coef.begin(), q_coef.end());
+  void* dco;
+  if ((rc = arena.alloc(std::max<size_t>(coefs.size(), 1) * 8, &dco))) return rc;
+  if ((rc = upload(dco, coefs.data(), coefs.size() * 8, s))) return rc;
+  st->p_coef = (const double*)dco;
+  st->q_coef = (const double*)dco + p_coef.size();
+  st->Tp = (int)p_coef.size();
+  st->Tq = (int)q_coef.size();
+
+  // twiddles: w_{M1}, w_{M2}, and the two-level table of w_L
+  const int64_t L = T.L;
+  const int64_t nlo = int64_t(1) << T.b, nhi = L >> T.b;
+  std::vector<double> w1(2 * T.M1), w2(2 * T.M2), wl(2 * L), wlo(2 * nlo), whi(2 * nhi);
+  twiddle_table(T.M1, w1.data());
+  twiddle_table(T.M2, w2.data());
+  twiddle_table(L, wl.data());
+  for (int64_t a = 0; a < nlo; ++a) { wlo[2 * a] = wl[2 * a]; wlo[2 * a + 1] = wl[2 * a + 1]; }
+  for (int64_t a = 0; a < nhi; ++a) {
+    whi[2 * a] = wl[2 * (a << T.b)];
+    whi[2 * a + 1] = wl[2 * (a << T.b) + 1];
+  }
+  const std::vector<double>* srcs[4] = {&w1, &w2, &wlo, &whi};
+  void** dsts[4] = {&st->twP1, &st->twP2, &st->twLlo, &st->twLhi};
+  for (int i = 0; i < 4; ++i) {
+    std::vector<unsigned char> b = twiddle_bytes(T.prec, *srcs[i]);
+    if ((rc = arena.alloc(b.size(), dsts[i]))) return rc;
+    if ((rc = upload(*dsts[i], b.data(), b.size(), s))) return rc;
+  }
+  return AGG_OK;
+}
+
+size_t slot_bytes(const PlanTables& T) {
+  size_t cs = complex_bytes(T.prec);
+  size_t ngroups = T.M2 / T.g;
+  return (size_t)T.u * T.M * cs + (size_t)T.M * cs + (size_t)T.u * ngroups * 8 + (size_t)T.u * 8 +
+         2 * (size_t)T.N * 8;
+}
+
+agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd) {
+  agg_status rc;
+  size_t cs = complex_bytes(T.prec);
+  size_t ngroups = T.M2 / T.g;
+  std::memset(sd, 0, sizeof(*sd));
+  if ((rc = arena.alloc((size_t)T.u * T.M * cs, &sd->Z1))) return rc;
+  if ((rc = arena.alloc((size_t)T.M * cs, &sd->V))) return rc;
+  if ((rc = arena.alloc((size_t)T.u * ngroups * 8, (void**)&sd->dots))) return rc;
+  if ((rc = arena.alloc((size_t)std::max(T.u, 1) * 8, (void**)&sd->G))) return rc;
+  if ((rc = arena.alloc((size_t)T.N * 8, (void**)&sd->k1))) return rc;
+  if ((rc = arena.alloc((size_t)T.N * 8, (void**)&sd->ntil))) return rc;
+  sd->cols = st.cols;
+  sd->p_off = st.p_off; sd->p_ids = st.p_ids; sd->p_coef = st.p_coef;
+  sd->q_off = st.q_off; sd->q_ids = st.q_ids; sd->q_kmode = st.q_kmode; sd->q_coef = st.q_coef;
+  sd->N = (int)T.N; sd->u = T.u; sd->Tp = st.Tp; sd->Tq = st.Tq;
+  sd->mode = CM_NONE; sd->row_on = 0; sd->dt = 0.0;
+  return AGG_OK;
+}
+
+LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots) {
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.slots = d_slots;
+  a.nslots = nslots;
+  a.mode = -1;
+  a.twP1 = st.twP1; a.twP2 = st.twP2; a.twLlo = st.twLlo; a.twLhi = st.twLhi;
+  a.M1 = T.M1; a.M2 = T.M2; a.g = T.g; a.b = T.b; a.L = T.L;
+  a.umax = std::max(T.u, 1);
+  return a;
+}
+
+}  // namespace agg
+
+using namespace agg;
+
+struct agg_plan {
+  PlanTables tab;
+  SharedTables st;
+  DeviceArena arena;
+  int batch = 1;
+  hipStream_t stream = nullptr;
+  SlotDesc* d_slots = nullptr;
+  double* d_part = nullptr;   // moment partials
+  int moment_blocks = 64;
+  bool trivial = false;       // no term with rank > 0: f == 0
+};
+
+extern "C" {
+
+const char* agg_last_error(void) { return g_err.c_str(); }
+
+agg_status agg_twiddles(int64_t P, double* out) {
+  if (P < 1 || (P & (P - 1)) != 0 || !out) return set_error(AGG_EINVAL, "P must be a power of two");
+  twiddle_table(P, out);
+  return AGG_OK;
+}
+
+agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
+                           agg_precision prec, int64_t* out, int64_t cap, int64_t* len) {
+  PlanTables T;
+  std::string err;
+  agg_status rc = plan_build(D, N, terms, nterms, prec, &T, &err);
+  if (rc != AGG_OK) return set_error(rc, err);
+  if (len) *len = (int64_t)T.flat.size();
+  if (!out || cap < (int64_t)T.flat.size()) return set_error(AGG_EINVAL, "output capacity too small");
+  std::memcpy(out, T.flat.data(), T.flat.size() * sizeof(int64_t));
+  return AGG_OK;
+}
+
+agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
+                           agg_precision prec, int32_t batch, void* hip_stream, agg_plan** out) {
+  if (!out) return set_error(AGG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");
+  agg_plan* p = new agg_plan();
+  std::string err;
+  agg_status rc = plan_build(D, N, terms, nterms, prec, &p->tab, &err);
+  if (rc != AGG_OK) { delete p; return set_error(rc, err); }
+  if (N > (int64_t)1 << 30) { delete p; return set_error(AGG_EUNSUPPORTED, "N too large"); }
+  p->batch = batch;
+  p->stream = (hipStream_t)hip_stream;
+  p->trivial = p->tab.u == 0;
+  if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
+  {
+    std::vector<SlotDesc> h(batch);
+    for (int b = 0; b < batch; ++b)
+      if ((rc = build_slot(p->tab, p->st, p->arena, &h[b]))) goto fail;
+    if ((rc = p->arena.alloc(sizeof(SlotDesc) * batch, (void**)&p->d_slots))) goto fail;
+    if ((rc = upload(p->d_slots, h.data(), sizeof(SlotDesc) * batch, p->stream))) goto fail;
+    if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
+  }
+  *out = p;
+  return AGG_OK;
+fail:
+  p->arena.release();
+  delete p;
+  return rc;
+}
+
+agg_status agg_plan_destroy(agg_plan* p) {
+  if (!p) return AGG_OK;
+  (void)hipStreamSynchronize(p->stream);
+  p->arena.release();
+  delete p;
+  return AGG_OK;
+}
+
+static agg_status run(agg_plan* p, int mode, double dt, double* state, double* outp, bool row) {
+  LaunchArgs a = base_args(p->tab, p->st, p->d_slots, p->batch);
+  a.mode = mode;
+  a.dt = dt;
+  a.ext_state = state;
+  a.ext_out = outp;
+  hipError_t e = row ? launch_row(p->tab.prec, a, p->stream) : launch_col(p->tab.prec, a, p->stream);
+  if (e != hipSuccess) return hip_fail(e, row ? "row pass launch" : "column pass launch");
+  return AGG_OK;
+}
+
+agg_status agg_rhs(agg_plan* p, const double* n, double* dndt) {
+  if (!p || !n || !dndt) return set_error(AGG_EINVAL, "NULL argument");
+  double* ns = const_cast<double*>(n);
+  if (p->trivial) {
+    hipError_t e = hipMemsetAsync(dndt, 0, sizeof(double) * p->tab.N * p->batch, p->stream);
+    return e == hipSuccess ? AGG_OK : hip_fail(e, "hipMemsetAsync");
+  }
+  agg_status rc;
+  if ((rc = run(p, CM_FWD, 0.0, ns, nullptr, false))) return rc;
+  if ((rc = run(p, CM_FWD, 0.0, ns, nullptr, true))) return rc;
+  return run(p, CM_RHS, 0.0, ns, dndt, false);
+}
+
+static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, double last_dt) {
+  if (nsteps <= 0 || p->trivial) return AGG_OK;
+  agg_status rc;
+  if ((rc = run(p, CM_FWD, 0.0, n, nullptr, false))) return rc;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    double h = (s == nsteps - 1) ? last_dt : dt;
+    if ((rc = run(p, CM_H1, h, n, nullptr, true))) return rc;
+    if ((rc = run(p, CM_H1, h, n, nullptr, false))) return rc;
+    if ((rc = run(p, CM_H2, h, n, nullptr, true))) return rc;
+    if ((rc = run(p, s == nsteps - 1 ? CM_H2 : CM_H2_FWD, h, n, nullptr, false))) return rc;
+  }
+  return AGG_OK;
+}
+
+agg_status agg_rk2_step(agg_plan* p, double* n, double dt) {
+  if (!p || !n) return set_error(AGG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AGG_EINVAL, "dt must be finite and > 0");
+  return heun_steps(p, n, dt, 1, dt);
+}
+
+static agg_status moments(agg_plan* p, const double* n, double* m0, double* m1, int64_t* nonfinite) {
+  int64_t total = p->tab.N * p->batch;
+  hipError_t e = launch_moments(n, total, p->tab.N, p->d_part, p->moment_blocks, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "moments launch");
+  std::vector<double> h(3 * p->moment_blocks);
+  e = hipMemcpyAsync(h.data(), p->d_part, h.size() * 8, hipMemcpyDeviceToHost, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int b = 0; b < p->moment_blocks; ++b) { a0 += h[3 * b]; a1 += h[3 * b + 1]; a2 += h[3 * b + 2]; }
+  *m0 = a0; *m1 = a1; *nonfinite = (int64_t)a2;
+  return AGG_OK;
+}
+
+agg_status agg_solve(agg_plan* p, double* n, double dt, double t_end, agg_solve_stats* st) {
+  if (!p || !n) return set_error(AGG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AGG_EINVAL, "dt must be finite and > 0");
+  if (!(t_end >= 0.0) || !std::isfinite(t_end)) return set_error(AGG_EINVAL, "t_end must be finite and >= 0");
+  int64_t nsteps;
+  double last;
+  time_grid(dt, t_end, &nsteps, &last);
+  agg_status rc;
+  int64_t nf0 = 0;
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    if ((rc = moments(p, n, &st->m0_initial, &st->m1_initial, &nf0))) return rc;
+  }
+  if ((rc = heun_steps(p, n, dt, nsteps, last))) return rc;
+  if (st) {
+    st->steps = nsteps;
+    st->rhs_evals = 2 * nsteps * p->batch;
+    st->t_final = nsteps == 0 ? 0.0 : (double)(nsteps - 1) * dt + last;
+    if ((rc = moments(p, n, &st->m0_final, &st->m1_final, &st->nonfinite))) return rc;
+    if (st->nonfinite) return set_error(AGG_ENONFINITE, "non-finite values in the final state");
+  }
+  return AGG_OK;
+}
+
+}  // extern "C"

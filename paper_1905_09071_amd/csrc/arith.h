@@ -1,0 +1,116 @@
+// Device arithmetic for the three spectral precisions of the library:
+//   double  - binary64 throughout
+//   float   - binary32 spectra, twiddles rounded from binary64
+//   ff      - float-float pairs (hi + lo) carried through the whole spectral
+//             path with error-free transforms (TwoSum, Fast2Sum, FMA-based
+//             TwoProd); about 44 significant bits at binary32 storage width x2.
+// The state vector, the loss-term dot products and all moment sums stay in
+// binary64 in every mode.
+//
+// Build note: everything here relies on IEEE round-to-nearest, no flush of
+// binary32 subnormals, and no reassociation (never compile with fast-math).
+// Contraction of a multiply and an add into one FMA is switched off inside
+// every float-float operation: fusing TwoProd's rounded product with the
+// following Fast2Sum (legal under -ffp-contract=fast once inlined) would
+// destroy the error terms.
+#pragma once
+#include <hip/hip_runtime.h>
+
+struct ff {
+  float hi, lo;
+};
+
+// ---- error-free transforms -------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  e = b - (s - a);
+}
+
+__device__ __forceinline__ ff operator+(ff a, ff b) {
+#pragma clang fp contract(off)
+  float s, e, t, f;
+  two_sum(a.hi, b.hi, s, e);
+  two_sum(a.lo, b.lo, t, f);
+  e += t;
+  fast_two_sum(s, e, s, e);
+  e += f;
+  ff r;
+  fast_two_sum(s, e, r.hi, r.lo);
+  return r;
+}
+__device__ __forceinline__ ff operator-(ff a) { return ff{-a.hi, -a.lo}; }
+__device__ __forceinline__ ff operator-(ff a, ff b) { return a + (-b); }
+__device__ __forceinline__ ff operator*(ff a, ff b) {
+#pragma clang fp contract(off)
+  float p = a.hi * b.hi;
+  float e = __builtin_fmaf(a.hi, b.hi, -p);
+  e = __builtin_fmaf(a.hi, b.lo, e);
+  e = __builtin_fmaf(a.lo, b.hi, e);
+  ff r;
+  fast_two_sum(p, e, r.hi, r.lo);
+  return r;
+}
+
+// ---- conversions -----------------------------------------------------------
+template <class T> struct Real;
+template <> struct Real<double> {
+  static __device__ __forceinline__ double from_d(double x) { return x; }
+  static __device__ __forceinline__ double to_d(double x) { return x; }
+  static __device__ __forceinline__ double zero() { return 0.0; }
+};
+template <> struct Real<float> {
+  static __device__ __forceinline__ float from_d(double x) { return (float)x; }
+  static __device__ __forceinline__ double to_d(float x) { return (double)x; }
+  static __device__ __forceinline__ float zero() { return 0.0f; }
+};
+template <> struct Real<ff> {
+  static __device__ __forceinline__ ff from_d(double x) {
+    float h = (float)x;
+    return ff{h, (float)(x - (double)h)};
+  }
+  static __device__ __forceinline__ double to_d(ff x) { return (double)x.hi + (double)x.lo; }
+  static __device__ __forceinline__ ff zero() { return ff{0.0f, 0.0f}; }
+};
+
+// ---- complex ---------------------------------------------------------------
+template <class T> struct cplx {
+  T re, im;
+};
+
+template <class T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+  return cplx<T>{a.re + b.re, a.im + b.im};
+}
+template <class T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+  return cplx<T>{a.re - b.re, a.im - b.im};
+}
+template <class T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return cplx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <class T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return cplx<T>{a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <class T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cplx<T>{a.re, -a.im}; }
+template <class T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {
+  return cplx<T>{a.re * s, a.im * s};
+}
+// multiply by +i and by -i
+template <class T> __device__ __forceinline__ cplx<T> cmul_i(cplx<T> a) { return cplx<T>{-a.im, a.re}; }
+template <class T> __device__ __forceinline__ cplx<T> cmul_negi(cplx<T> a) { return cplx<T>{a.im, -a.re}; }
+
+template <class T> __device__ __forceinline__ cplx<T> czero() {
+  return cplx<T>{Real<T>::zero(), Real<T>::zero()};
+}
+
+// Halving is exact in every format (barring underflow), so it is a plain scale.
+template <class T> __device__ __forceinline__ T half_of(T x);
+template <> __device__ __forceinline__ double half_of(double x) { return 0.5 * x; }
+template <> __device__ __forceinline__ float half_of(float x) { return 0.5f * x; }
+template <> __device__ __forceinline__ ff half_of(ff x) { return ff{0.5f * x.hi, 0.5f * x.lo}; }

@@ -1,0 +1,49 @@
+// Library-internal helpers shared by the plan API and the serving engine.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/agg.h"
+#include "kernels.h"
+#include "planner.h"
+
+namespace agg {
+
+agg_status set_error(agg_status code, const std::string& msg);
+agg_status hip_fail(hipError_t e, const char* what);
+
+// Device allocations owned by one plan or one engine request.
+struct DeviceArena {
+  std::vector<void*> ptrs;
+  size_t total = 0;
+  agg_status alloc(size_t bytes, void** p);
+  void release();
+};
+
+// Device copies of everything a kernel set needs that is shared by all the
+// states using it: distinct columns, term tables, twiddles.
+struct SharedTables {
+  const PlanTables* tab = nullptr;
+  double* cols = nullptr;
+  const int *p_off = nullptr, *p_ids = nullptr, *q_off = nullptr, *q_ids = nullptr, *q_kmode = nullptr;
+  const double *p_coef = nullptr, *q_coef = nullptr;
+  int Tp = 0, Tq = 0;
+  void *twP1 = nullptr, *twP2 = nullptr, *twLlo = nullptr, *twLhi = nullptr;
+};
+
+agg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st);
+agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd);
+size_t slot_bytes(const PlanTables& T);
+LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots);
+
+// kernels.hip
+hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s);
+hipError_t launch_row(int prec, const LaunchArgs& a, hipStream_t s);
+hipError_t launch_moments(const double* n, int64_t total, int64_t N, double* part, int nblocks,
+                          hipStream_t s);
+size_t row_smem_bytes(int prec, int umax, int M2);
+
+}  // namespace agg

@@ -1,0 +1,74 @@
+// Shared host/device definitions of the RHS pipeline.
+//
+// The right-hand side is computed with real transforms of length L carried by
+// complex transforms of length M = L/2 (even/odd packing), each split as
+// M = M1*M2 (four-step).  Index conventions:
+//   time side:  j = j2 + M2*j1   (z[j] = x[2j] + i x[2j+1], x indexed by size)
+//   frequency:  k = k1 + M1*k2
+// Buffers per state (slot):
+//   Z1[c][k1][j2]  forward column transforms of the u weighted columns, already
+//                  multiplied by w_M^(j2*k1)
+//   V [k1][j2]     inverse row transforms of the combined spectrum, multiplied by
+//                  w_M^(-j2*k1)
+// The column kernel turns V into the gain term, adds the loss term, applies the
+// requested state update and (optionally) starts the next evaluation by forming
+// and transforming the weighted columns of the new state.  The row kernel does
+// everything between the two column passes.
+#pragma once
+#include <cstdint>
+
+namespace agg {
+
+// What the column kernel does for a slot.
+enum ColMode : int {
+  CM_NONE = 0,      // nothing
+  CM_FWD = 1,       // forward only, from the state
+  CM_RHS = 2,       // inverse + epilogue: out = f(state)
+  CM_H1 = 3,        // inverse + epilogue: k1 = f(n), n~ = n + dt k1, forward of n~
+  CM_H2 = 4,        // inverse + epilogue: n <- n + dt/2 (k1 + f(n~))
+  CM_H2_FWD = 5,    // as CM_H2, then forward of the new n
+};
+
+__host__ __device__ inline bool mode_has_inverse(int m) { return m >= CM_RHS; }
+__host__ __device__ inline bool mode_has_forward(int m) { return m == CM_FWD || m == CM_H1 || m == CM_H2_FWD; }
+
+struct SlotDesc {
+  double* n_state;        // state (used when the launch passes no external state)
+  double* k1;             // Heun stage-1 slope, N
+  double* ntil;           // Heun stage-1 state n~, N
+  const double* cols;     // u distinct factor columns, N each (binary64)
+  void* Z1;               // u*M stored complex values
+  void* V;                // M stored complex values
+  double* dots;           // u*ngroups partial dot products (column kernel -> row kernel)
+  double* G;              // u loss-term weights of the current evaluation
+  const int* p_off;       // Tp+1 offsets into p_ids
+  const int* p_ids;       // column ids of each gain term
+  const double* p_coef;   // multiplicity / d!
+  const int* q_off;       // Tq+1 offsets into q_ids
+  const int* q_ids;       // ids of modes 1..d-1 of each loss term
+  const int* q_kmode;     // k-mode column id of each loss term
+  const double* q_coef;   // multiplicity / (d-1)!
+  int N, u, Tp, Tq;
+  int mode;               // per-slot column mode (when the launch mode is < 0)
+  int row_on;             // per-slot row pass switch (when the launch mode is < 0)
+  double dt;              // per-slot step (when the launch mode is < 0)
+  double* out;            // per-slot RHS output (CM_RHS without external output)
+};
+
+struct LaunchArgs {
+  const SlotDesc* slots;
+  int nslots;
+  int mode;               // >= 0: same mode for all slots; < 0: per slot
+  double dt;
+  double* ext_state;      // batch-contiguous state (nullptr: slot n_state)
+  double* ext_out;        // batch-contiguous RHS output (CM_RHS)
+  const void* twP1;       // w_{M1}^e, e < M1
+  const void* twP2;       // w_{M2}^e, e < M2
+  const void* twLlo;      // w_L^a,       a < 2^b
+  const void* twLhi;      // w_L^(a 2^b), a < L/2^b
+  int M1, M2, g, b;
+  int64_t L;
+  int umax;               // largest u among the slots (row kernel LDS sizing)
+};
+
+}  // namespace agg

