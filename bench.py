@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-particle aggregation right-hand side on one MI355X.
+
+Workload (a "step" = one Heun step = two right-hand-side evaluations over the
+whole pipeline): D = 4, N = 65536, ballistic-like kernel
+C^(d) = sum_{m != l} (i_m/i_l)^0.4 in CP form, n_k(0) uniform random on
+k in [1, 16] (PCG64 seed 3), Heun step dt = 5e-4; 1000 steps are the whole
+t = 0.5 solve.  The state is resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  `value` is right-hand-side evaluations per second in
+the primary precision (float-float compensated by default); the binary64 and
+binary32 rates of the same workload are reported beside it, with the serving
+sample's latency percentiles and the oracle's CPU rate.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PREC_BYTES = {"fp64": 16, "fp32": 8, "fp32c": 16}
+PASS_NAMES = {0: "forward column pass", 1: "row pass", 2: "inverse column pass + f",
+              3: "fused column pass (inverse + Heun + forward)"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(which: int, N: int, u: int, M: int, cs: int) -> float:
+    """Algorithmic HBM bytes of one launch of a pass for one state.
+
+    Spectra: each of the u forward half-length spectra (M stored complex values
+    of cs bytes) is written once and read once, and the combined spectrum is
+    written once and read once; state-sized vectors are binary64.
+      0 forward column pass: read n and u columns, write u spectra
+      1 row pass:            read u spectra, write the combined spectrum
+      2 inverse column + f:  read combined spectrum, n, u columns; write f
+      3 fused column pass:   read combined spectrum, n, u columns;
+                             write k1, n~ and u spectra
+    """
+    if which == 0:
+        return 8.0 * N * (1 + u) + u * M * cs
+    if which == 1:
+        return u * M * cs + M * cs
+    if which == 2:
+        return M * cs + 8.0 * N * (1 + u) + 8.0 * N
+    return M * cs + 8.0 * N * (1 + u) + 2 * 8.0 * N + u * M * cs
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_lds.h", "arith.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1905_09071_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(which: int, prec: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_c3.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch", {}).get(f"{prec}:{which}")
+
+
+def time_steps(plan, n, dt, steps, warmup, torch):
+    plan.solve(n, dt, warmup * dt, stats=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    plan.solve(n, dt, steps * dt, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1000.0, wall
+
+
+def cpu_baseline(c, budget_s: float):
+    """The oracle (per-rank numpy FFT evaluation) on the host, bounded sample."""
+    import numpy as np
+    import oracle
+    import synth
+    n = synth.n0_random_dense(c["N"], 5, decay=1e-4)
+    evals = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.rhs_fft(c["D"], c["N"], c["kernel"], n)
+        evals += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or evals >= 40:
+            break
+    _ = np
+    return evals / el, evals, el
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64", "fp32"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU sample budget (0 = skip)")
+    ap.add_argument("--serving", type=int, default=64, help="requests in the serving sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1905_09071_amd as agg
+    import synth
+
+    c = synth.config("C3")
+    D, N, dt = c["D"], c["N"], c["dt"]
+    tables = agg.plan_tables(D, N, c["kernel"], args.prec)
+    L, M1, M2, g, u = (int(x) for x in tables[:5])
+    M = L // 2
+    log(f"[bench] C3 D={D} N={N} L={L} M1={M1} M2={M2} g={g} u={u} steps={args.steps} warmup={args.warmup}")
+
+    results = {}
+    order = [args.prec] + [p for p in ("fp64", "fp32", "fp32c") if p != args.prec]
+    for prec in order:
+        plan = agg.Plan(D, N, c["kernel"], prec)
+        n = torch.tensor(c["n0"], dtype=torch.float64, device="cuda:0")
+        t_gpu, t_wall = time_steps(plan, n, dt, args.steps, args.warmup, torch)
+        rate = 2 * args.steps / t_gpu
+        passes = {w: plan.profile_pass(n, w, reps=200) for w in (0, 1, 2, 3)}
+        results[prec] = dict(seconds=t_gpu, wall=t_wall, rhs_per_s=rate, passes_us=passes)
+        log(f"[bench] {prec}: {args.steps} steps in {t_gpu*1e3:.2f} ms (wall {t_wall*1e3:.2f}) -> "
+            f"{rate:.1f} RHS/s; pass us: " + ", ".join(f"{w}:{v:.2f}" for w, v in passes.items()))
+        plan.close()
+        del n
+
+    prim = results[args.prec]
+    cs = PREC_BYTES[args.prec]
+    # dominant kernel of a time step: the pass with the largest device time
+    dom = max((1, 3), key=lambda w: prim["passes_us"][w])
+    bytes_dom = pass_bytes(dom, N, u, M, cs)
+    achieved = bytes_dom / (prim["passes_us"][dom] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, args.prec),
+                "kernel": PASS_NAMES[dom], "bytes_per_launch": bytes_dom,
+                "us_per_launch": round(prim["passes_us"][dom], 3)}
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("[bench] cpu baseline (oracle) ...")
+        rate, evals, el = cpu_baseline(c, args.cpu_seconds)
+        cpu = {"value": round(rate, 4), "unit": "RHS evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{evals} oracle RHS evaluations (per-rank numpy FFT, D=4 N=65536, dense state) "
+                         f"in {el:.1f} s on one host thread"}
+
+    serving = None
+    if args.serving > 0:
+        from serving_bench import run_serving
+        serving = run_serving(args.serving, log=log)
+
+    ms_per_step = prim["seconds"] / args.steps * 1e3
+    line = {
+        "metric": "RHS evals/s at D=4 N=65536 (FP32-comp vs FP64) + serving p50/p99 latency",
+        "value": round(prim["rhs_per_s"], 2),
+        "unit": "RHS evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32c": "f32x2 (float-float)", "fp64": "f64", "fp32": "f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "C3: D=4 N=65536 ballistic a=0.4 CP (u=3 distinct columns), "
+                               "n0 uniform on [1,16] seed 3, Heun dt=5e-4, one state",
+                   "L": L, "M1": M1, "M2": M2, "parallelism": "single GPU"},
+        "rhs_per_s": {p: round(r["rhs_per_s"], 2) for p, r in results.items()},
+        "ratio_fp32c_vs_fp64": round(results["fp32c"]["rhs_per_s"] / results["fp64"]["rhs_per_s"], 4),
+        "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "serving": serving,
+    }
+    _ = np
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

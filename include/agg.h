@@ -110,6 +110,20 @@ typedef struct {
  * written).  Errors: AGG_EINVAL for dt <= 0, t_end < 0, or non-finite. */
 agg_status agg_solve(agg_plan* plan, double* n, double dt, double t_end, agg_solve_stats* st);
 
+/* ---- timing aid ------------------------------------------------------------
+ * Runs one pass of the evaluation pipeline `reps` times back to back on the
+ * plan's stream for the batch state n (device, batch*N; not modified) and
+ * writes the mean device time per launch in microseconds, measured with HIP
+ * events on that stream.  A full right-hand side is evaluated first so every
+ * intermediate buffer is valid.  pass: 0 forward column pass (weighting,
+ * column transforms, dot products), 1 row pass (row transforms, spectral
+ * combine, inverse row transforms), 2 inverse column pass with the f epilogue,
+ * 3 fused column pass of a time step (inverse + epilogue + Heun stage-1 update
+ * + forward pass of the updated state).  Synchronises the stream.
+ * Errors: AGG_EINVAL (NULL, pass outside [0,3], reps < 1), AGG_EHIP. */
+agg_status agg_profile_pass(agg_plan* plan, const double* n, int32_t pass, int32_t reps,
+                            double* us_per_launch);
+
 /* ---- introspection (host only: no device is touched) ----------------------
  * agg_plan_tables writes the plan's integer tables as int64 (layout:
  * [L, M1, M2, g, u, Tp, Tq, De, column id per (d, m, r) in scan order d, m, r,

@@ -105,6 +105,13 @@ class Plan:
         check(lib().agg_rk2_step(self._h, _check_state(n, self.batch * self.N), float(dt)))
         return n
 
+    def profile_pass(self, n, which: int, reps: int = 50) -> float:
+        """Mean device microseconds per launch of one pipeline pass (see agg.h)."""
+        us = ctypes.c_double()
+        check(lib().agg_profile_pass(self._h, _check_state(n, self.batch * self.N), int(which), int(reps),
+                                     ctypes.byref(us)))
+        return us.value
+
     def solve(self, n, dt: float, t_end: float, stats: bool = True):
         st = agg_solve_stats()
         rc = lib().agg_solve(self._h, _check_state(n, self.batch * self.N), float(dt), float(t_end),

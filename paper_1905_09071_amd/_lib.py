@@ -50,6 +50,8 @@ EXPORTS = [
     ("agg_rk2_step", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
     ("agg_solve", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(agg_solve_stats)]),
+    ("agg_profile_pass", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double)]),
     ("agg_plan_tables", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_term), ctypes.c_int32,
                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int64)]),

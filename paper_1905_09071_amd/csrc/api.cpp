@@ -209,6 +209,7 @@ struct agg_plan {
   hipStream_t stream = nullptr;
   SlotDesc* d_slots = nullptr;
   double* d_part = nullptr;   // moment partials
+  double* d_scratch = nullptr;  // batch*N doubles: output of timed inverse passes
   int moment_blocks = 64;
   bool trivial = false;       // no term with rank > 0: f == 0
 };
@@ -256,6 +257,7 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
     if ((rc = p->arena.alloc(sizeof(SlotDesc) * batch, (void**)&p->d_slots))) goto fail;
     if ((rc = upload(p->d_slots, h.data(), sizeof(SlotDesc) * batch, p->stream))) goto fail;
     if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
+    if ((rc = p->arena.alloc(sizeof(double) * p->tab.N * batch, (void**)&p->d_scratch))) goto fail;
   }
   *out = p;
   return AGG_OK;
@@ -353,6 +355,33 @@ agg_status agg_solve(agg_plan* p, double* n, double dt, double t_end, agg_solve_
     if ((rc = moments(p, n, &st->m0_final, &st->m1_final, &st->nonfinite))) return rc;
     if (st->nonfinite) return set_error(AGG_ENONFINITE, "non-finite values in the final state");
   }
+  return AGG_OK;
+}
+
+agg_status agg_profile_pass(agg_plan* p, const double* n, int32_t pass, int32_t reps, double* us) {
+  if (!p || !n || !us || pass < 0 || pass > 3 || reps < 1) return set_error(AGG_EINVAL, "bad argument");
+  *us = 0.0;
+  if (p->trivial) return AGG_OK;
+  double* ns = const_cast<double*>(n);
+  agg_status rc;
+  if ((rc = agg_rhs(p, n, p->d_scratch))) return rc;
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  static const int modes[4] = {CM_FWD, CM_FWD, CM_RHS, CM_H1};
+  e = hipEventRecord(e0, p->stream);
+  for (int r = 0; r < reps && e == hipSuccess && rc == AGG_OK; ++r)
+    rc = run(p, modes[pass], 1e-6, ns, p->d_scratch, pass == 1);
+  if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != AGG_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "timing events");
+  *us = 1000.0 * (double)ms / reps;
   return AGG_OK;
 }
 

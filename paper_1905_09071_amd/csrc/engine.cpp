@@ -60,7 +60,8 @@ using BucketKey = std::tuple<int64_t, int, int, int, int>;   // L, M1, M2, g, pr
 
 struct Engine {
   agg_engine_config cfg{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // all kernels and result copies
+  hipStream_t up_stream = nullptr;   // admission uploads (synchronised per upload)
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv;
@@ -71,7 +72,7 @@ struct Engine {
   std::vector<std::unique_ptr<Request>> finishing;            // last stage enqueued
   std::unordered_map<uint64_t, std::unique_ptr<Request>> done;
   std::unordered_map<uint64_t, int> known;                    // ticket -> 1 while not polled
-  std::atomic<int64_t> n_completed{0}, bytes_in_use{0};
+  std::atomic<int64_t> n_completed{0}, bytes_in_use{0}, n_active{0};
   // descriptor staging ring (pinned host -> device), one entry per tick
   static constexpr int kRing = 8;
   SlotDesc* h_desc[kRing] = {nullptr};
@@ -92,10 +93,10 @@ struct Engine {
 
 agg_status Engine::setup_device(Request& r) {
   agg_status rc;
-  if ((rc = build_shared(r.tab, stream, r.arena, &r.st))) return rc;
+  if ((rc = build_shared(r.tab, up_stream, r.arena, &r.st))) return rc;
   if ((rc = build_slot(r.tab, r.st, r.arena, &r.sd))) return rc;
   if ((rc = r.arena.alloc(sizeof(double) * r.tab.N, (void**)&r.d_n))) return rc;
-  if ((rc = upload(r.d_n, r.n0.data(), sizeof(double) * r.tab.N, stream))) return rc;
+  if ((rc = upload(r.d_n, r.n0.data(), sizeof(double) * r.tab.N, up_stream))) return rc;
   r.sd.n_state = r.d_n;
   hipError_t e = hipHostMalloc((void**)&r.h_out, sizeof(double) * r.tab.N, hipHostMallocDefault);
   if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
@@ -148,6 +149,7 @@ void Engine::admit() {
       continue;
     }
     bytes_in_use += (int64_t)r.footprint;
+    n_active++;
     running.push_back(std::move(rp));
   }
 }
@@ -238,6 +240,7 @@ void Engine::retire(bool block) {
     if (q != hipSuccess) r.status = AGG_EHIP;
     release_device(r);
     bytes_in_use -= (int64_t)r.footprint;
+    n_active--;
     std::lock_guard<std::mutex> lk(mu);
     n_completed++;
     done[r.ticket] = std::move(rp);
@@ -262,6 +265,7 @@ void Engine::run() {
     retire(idle_launches && !finishing.empty());
   }
   (void)hipStreamSynchronize(stream);
+  (void)hipStreamSynchronize(up_stream);
   for (auto* v : {&running, &finishing})
     for (auto& rp : *v) release_device(*rp);
 }
@@ -294,6 +298,7 @@ agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out) {
   g.cap_slots = c.max_slots;
   e = hipSetDevice(c.device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.up_stream, hipStreamNonBlocking);
   for (int i = 0; i < Engine::kRing && e == hipSuccess; ++i) {
     e = hipHostMalloc((void**)&g.h_desc[i], sizeof(SlotDesc) * c.max_slots, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&g.d_desc[i], sizeof(SlotDesc) * c.max_slots);
@@ -307,6 +312,7 @@ agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out) {
       if (g.ring_ev[i]) (void)hipEventDestroy(g.ring_ev[i]);
     }
     if (g.stream) (void)hipStreamDestroy(g.stream);
+    if (g.up_stream) (void)hipStreamDestroy(g.up_stream);
     delete E;
     return rc;
   }
@@ -330,6 +336,7 @@ agg_status agg_engine_destroy(agg_engine* E) {
     if (g.ring_ev[i]) (void)hipEventDestroy(g.ring_ev[i]);
   }
   if (g.stream) (void)hipStreamDestroy(g.stream);
+  if (g.up_stream) (void)hipStreamDestroy(g.up_stream);
   delete E;
   return AGG_OK;
 }
@@ -400,7 +407,7 @@ agg_status agg_engine_counters(agg_engine* E, int64_t* completed, int64_t* runni
   Engine& g = E->eng;
   std::lock_guard<std::mutex> lk(g.mu);
   if (completed) *completed = g.n_completed.load();
-  if (running) *running = (int64_t)(g.running.size() + g.finishing.size());
+  if (running) *running = g.n_active.load();
   if (queued) *queued = (int64_t)g.queue.size();
   if (bytes_in_use) *bytes_in_use = g.bytes_in_use.load();
   return AGG_OK;

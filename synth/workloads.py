@@ -21,6 +21,7 @@ __all__ = [
     "kernel_additive", "kernel_random", "kernel_random_symmetric",
     "kernel_generalized_brownian", "n0_monodisperse", "n0_exponential",
     "n0_uniform_head", "n0_random_dense", "CONFIGS", "config", "build_kernel", "build_n0",
+    "serving_requests",
 ]
 
 
@@ -208,3 +209,29 @@ def config(name: str) -> dict:
         c["n0"] = build_n0(c["N"], c["n0"])
     c["name"] = name
     return c
+
+
+def serving_requests(count: int, seed: int = 4, t_end_range=(1.0, 20.0), dt: float = 1e-3,
+                     log2n_range=(10, 16), kmax: int = 16, steps_range=None):
+    """Solve requests shaped like the serving workload: N = 2^round(U[10,16]),
+    D uniform in {2,3,4}, ballistic-like kernel with a ~ U[0, 0.9], initial data
+    uniform on [1, kmax] (seeded per request), t_end ~ U[t_end_range].
+
+    With ``steps_range`` the request instead takes a step size inside explicit
+    Heun's stability interval, dt = min(dt, 1/(D^2 N^a)) (the loss rate of the
+    largest size grows like D^2 N^a for this kernel), and a step count drawn
+    from U[steps_range], so t_end = steps * dt."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        N = 1 << int(round(rng.uniform(*log2n_range)))
+        D = int(rng.integers(2, 5))
+        a = float(rng.uniform(0.0, 0.9))
+        t_end = float(rng.uniform(*t_end_range))
+        h = dt
+        if steps_range is not None:
+            h = min(dt, 1.0 / (D * D * float(N) ** a))
+            t_end = int(rng.integers(steps_range[0], steps_range[1] + 1)) * h
+        out.append(dict(D=D, N=N, a=a, t_end=t_end, dt=h, n0_seed=1000 + i,
+                        kernel=kernel_ballistic(D, N, a), n0=n0_uniform_head(N, 1000 + i, kmax)))
+    return out

@@ -1,0 +1,104 @@
+"""Serving engine on the GPU: requests of uneven N, D, kernel and length run
+concurrently (continuous batching) and each result equals the same solve run
+alone through agg_solve; admission, rejection and ticket handling."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+agg = pytest.importorskip("paper_1905_09071_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def alone(r, prec):
+    plan = agg.Plan(r["D"], r["N"], r["kernel"], prec)
+    n = torch.tensor(r["n0"], dtype=torch.float64, device="cuda:0")
+    plan.solve(n, r["dt"], r["t_end"])
+    out = n.cpu().numpy()
+    plan.close()
+    return out
+
+
+def drain(eng, tickets, Ns, limit=120.0):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        for t, N in zip(tickets, Ns):
+            if t not in res:
+                rc, out, st = eng.poll(t, N)
+                if rc != agg.AGG_PENDING:
+                    res[t] = (rc, out, st)
+        assert time.time() - t0 < limit, "engine did not finish"
+        time.sleep(0.001)
+    return res
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_mixed_requests_equal_alone(prec):
+    reqs = synth.serving_requests(10, seed=11, t_end_range=(0.005, 0.05), log2n_range=(10, 14))
+    # a second copy of the first request arrives later, while others run
+    eng = agg.Engine(0)
+    tickets = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in reqs[:6]]
+    time.sleep(0.002)
+    tickets += [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in reqs[6:]]
+    res = drain(eng, tickets, [r["N"] for r in reqs])
+    c = eng.counters()
+    eng.close()
+    assert c["completed"] == len(reqs) and c["running"] == 0 and c["queued"] == 0
+    for r, t in zip(reqs, tickets):
+        rc, out, st = res[t]
+        assert rc == agg.AGG_OK
+        ref = alone(r, prec)
+        say(f"[serve] D={r['D']} N={r['N']} a={r['a']:.2f} steps={st.steps} "
+            f"maxdiff={np.max(np.abs(out - ref)):.3e}")
+        assert st.steps == len(__import__("oracle").time_grid(r["dt"], r["t_end"]))
+        assert np.array_equal(out, ref)        # slot arithmetic is independent of neighbours
+        assert st.t_submit <= st.t_admit <= st.t_finish
+
+
+def test_budget_and_errors():
+    N = 4096
+    k = synth.kernel_ballistic(3, N, 0.5)
+    n0 = synth.n0_uniform_head(N, 1)
+    eng = agg.Engine(0, mem_budget=256 << 10)      # 256 KiB: too small for this request
+    with pytest.raises(agg.AggError) as e:
+        eng.submit(3, N, k, n0, 1e-3, 0.01, "fp64")
+    assert e.value.status == agg.AGG_ENOMEM
+    eng.close()
+    eng = agg.Engine(0)
+    bad = n0.copy()
+    bad[3] = np.nan
+    with pytest.raises(agg.AggError) as e:
+        eng.submit(3, N, k, bad, 1e-3, 0.01, "fp64")
+    assert e.value.status == agg.AGG_ENONFINITE
+    with pytest.raises(agg.AggError) as e:
+        eng.poll(987654321, N)
+    assert e.value.status == agg.AGG_ENOTFOUND
+    # t_end = 0: the result is the initial state
+    t = eng.submit(3, N, k, n0, 1e-3, 0.0, "fp64")
+    res = drain(eng, [t], [N])
+    assert res[t][0] == agg.AGG_OK and np.array_equal(res[t][1], n0)
+    eng.close()
+
+
+def test_fifo_admission_under_tight_budget():
+    """With room for about one request at a time every request still finishes,
+    in submission order of admission."""
+    reqs = synth.serving_requests(4, seed=12, t_end_range=(0.003, 0.01), log2n_range=(12, 12))
+    eng = agg.Engine(0, mem_budget=3 << 20)
+    tickets = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], "fp64") for r in reqs]
+    res = drain(eng, tickets, [r["N"] for r in reqs])
+    eng.close()
+    admits = [res[t][2].t_admit for t in tickets]
+    assert all(res[t][0] == agg.AGG_OK for t in tickets)
+    assert admits == sorted(admits)
