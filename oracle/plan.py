@@ -20,7 +20,7 @@ P6  Two-pass split: lg = log2 M; M1 = 2^ceil(lg/2), M2 = M/M1.  With cs = 16
     bytes per stored complex (fp64, fp32c) or 8 (fp32): while u*2*M2*cs > 64 KiB
     and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048 or
     u*2*M2*cs > 144 KiB.
-P7  Column tile: g = min(M2, max(1, 2048 / M1)) adjacent columns per workgroup.
+P7  Column tile: g = min(M2, max(1, 1024 / M1)) adjacent columns per workgroup.
 
 Flat table (int64), as exported for comparison:
     [L, M1, M2, g, u, Tp, Tq, De,
@@ -92,7 +92,7 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64"):
         M2 //= 2
     if M1 > 2048 or u * 2 * M2 * cs > 147456:
         raise Unsupported(f"no two-pass split for L={L} with u={u} columns")
-    g = min(M2, max(1, 2048 // M1))
+    g = min(M2, max(1, 1024 // M1))
 
     flat = [L, M1, M2, g, u, len(pterms), len(qterms), De] + colmap
     for key, mult in pterms:

@@ -41,7 +41,7 @@ def _hipcc():
 
 def _compile(src, device, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc()] + COMMON + (DEVICE if device else ["-D__HIP_PLATFORM_AMD__"]) + [
+    cmd = [_hipcc()] + COMMON + (DEVICE if device else ["-D__HIP_PLATFORM_AMD__", "--offload-arch=" + ARCH]) + [
         "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -110,30 +110,28 @@ agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, 
     q_km.push_back(T.q_kmode[t]);
     q_coef.push_back((double)T.q_mult[t] / factorial(T.q_d[t] - 1));
   }
-  std::vector<unsigned char> ints;
+  std::vector<int> blob;
   auto put = [&](const std::vector<int>& v) {
-    size_t off = ints.size();
-    ints.resize(off + std::max<size_t>(v.size(), 1) * 4);
-    if (!v.empty()) std::memcpy(&ints[off], v.data(), v.size() * 4);
+    int off = (int)blob.size();
+    blob.insert(blob.end(), v.begin(), v.end());
     return off;
   };
-  size_t o_poff = put(p_off), o_pids = put(p_ids), o_qoff = put(q_off), o_qids = put(q_ids),
-         o_qkm = put(q_km);
+  put(p_off);
+  st->o_pids = put(p_ids);
+  st->o_qoff = put(q_off);
+  st->o_qids = put(q_ids);
+  st->o_qkm = put(q_km);
+  st->ntab = (int)blob.size();
   void* dints;
-  if ((rc = arena.alloc(ints.size(), &dints))) return rc;
-  if ((rc = upload(dints, ints.data(), ints.size(), s))) return rc;
-  st->p_off = (const int*)((char*)dints + o_poff);
-  st->p_ids = (const int*)((char*)dints + o_pids);
-  st->q_off = (const int*)((char*)dints + o_qoff);
-  st->q_ids = (const int*)((char*)dints + o_qids);
-  st->q_kmode = (const int*)((char*)dints + o_qkm);
+  if ((rc = arena.alloc(blob.size() * 4, &dints))) return rc;
+  if ((rc = upload(dints, blob.data(), blob.size() * 4, s))) return rc;
+  st->tabs = (const int*)dints;
   std::vector<double> coefs(p_coef);
   coefs.insert(coefs.end(), q_coef.begin(), q_coef.end());
   void* dco;
   if ((rc = arena.alloc(std::max<size_t>(coefs.size(), 1) * 8, &dco))) return rc;
   if ((rc = upload(dco, coefs.data(), coefs.size() * 8, s))) return rc;
-  st->p_coef = (const double*)dco;
-  st->q_coef = (const double*)dco + p_coef.size();
+  st->coef = (const double*)dco;
   st->Tp = (int)p_coef.size();
   st->Tq = (int)q_coef.size();
 
@@ -166,34 +164,53 @@ size_t slot_bytes(const PlanTables& T) {
          2 * (size_t)T.N * 8;
 }
 
-agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd) {
+// Buffers of `batch` slots sharing one kernel set, each kind carved from one
+// allocation; slot b's buffers sit at base + b*stride.
+agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena& arena, int batch,
+                       SlotDesc* sd, SlotStride* stride) {
   agg_status rc;
   size_t cs = complex_bytes(T.prec);
   size_t ngroups = T.M2 / T.g;
+  SlotStride s;
+  s.Z1 = (int64_t)((size_t)T.u * T.M * cs);
+  s.V = (int64_t)((size_t)T.M * cs);
+  s.dots = (int64_t)((size_t)T.u * ngroups * 8);
+  s.G = (int64_t)((size_t)std::max(T.u, 1) * 8);
+  s.k1 = s.ntil = (int64_t)((size_t)T.N * 8);
   std::memset(sd, 0, sizeof(*sd));
-  if ((rc = arena.alloc((size_t)T.u * T.M * cs, &sd->Z1))) return rc;
-  if ((rc = arena.alloc((size_t)T.M * cs, &sd->V))) return rc;
-  if ((rc = arena.alloc((size_t)T.u * ngroups * 8, (void**)&sd->dots))) return rc;
-  if ((rc = arena.alloc((size_t)std::max(T.u, 1) * 8, (void**)&sd->G))) return rc;
-  if ((rc = arena.alloc((size_t)T.N * 8, (void**)&sd->k1))) return rc;
-  if ((rc = arena.alloc((size_t)T.N * 8, (void**)&sd->ntil))) return rc;
+  if ((rc = arena.alloc((size_t)s.Z1 * batch, &sd->Z1))) return rc;
+  if ((rc = arena.alloc((size_t)s.V * batch, &sd->V))) return rc;
+  if ((rc = arena.alloc((size_t)s.dots * batch, (void**)&sd->dots))) return rc;
+  if ((rc = arena.alloc((size_t)s.G * batch, (void**)&sd->G))) return rc;
+  if ((rc = arena.alloc((size_t)s.k1 * batch, (void**)&sd->k1))) return rc;
+  if ((rc = arena.alloc((size_t)s.ntil * batch, (void**)&sd->ntil))) return rc;
   sd->cols = st.cols;
-  sd->p_off = st.p_off; sd->p_ids = st.p_ids; sd->p_coef = st.p_coef;
-  sd->q_off = st.q_off; sd->q_ids = st.q_ids; sd->q_kmode = st.q_kmode; sd->q_coef = st.q_coef;
+  sd->tab = st.tabs; sd->coef = st.coef; sd->ntab = st.ntab;
+  sd->o_pids = st.o_pids; sd->o_qoff = st.o_qoff; sd->o_qids = st.o_qids; sd->o_qkm = st.o_qkm;
   sd->N = (int)T.N; sd->u = T.u; sd->Tp = st.Tp; sd->Tq = st.Tq;
   sd->mode = CM_NONE; sd->row_on = 0; sd->dt = 0.0;
+  if (stride) *stride = s;
   return AGG_OK;
+}
+
+agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd) {
+  return build_slots(T, st, arena, 1, sd, nullptr);
 }
 
 LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots) {
   LaunchArgs a;
-  std::memset(&a, 0, sizeof(a));
+  std::memset((void*)&a, 0, sizeof(a));
   a.slots = d_slots;
   a.nslots = nslots;
   a.mode = -1;
   a.twP1 = st.twP1; a.twP2 = st.twP2; a.twLlo = st.twLlo; a.twLhi = st.twLhi;
   a.M1 = T.M1; a.M2 = T.M2; a.g = T.g; a.b = T.b; a.L = T.L;
   a.umax = std::max(T.u, 1);
+  a.ub = col_batch(T.prec, T.M1, T.u, nslots * (T.M2 / T.g));
+  a.lgg = 0;
+  while ((1 << a.lgg) < T.g) ++a.lgg;
+  a.tab_max = st.ntab;
+  a.coef_max = st.Tp + st.Tq;
   return a;
 }
 
@@ -207,7 +224,8 @@ struct agg_plan {
   DeviceArena arena;
   int batch = 1;
   hipStream_t stream = nullptr;
-  SlotDesc* d_slots = nullptr;
+  SlotDesc base;              // slot 0; slot b is base moved by b*stride
+  SlotStride stride;
   double* d_part = nullptr;   // moment partials
   double* d_scratch = nullptr;  // batch*N doubles: output of timed inverse passes
   int moment_blocks = 64;
@@ -251,11 +269,7 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
   p->trivial = p->tab.u == 0;
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
   {
-    std::vector<SlotDesc> h(batch);
-    for (int b = 0; b < batch; ++b)
-      if ((rc = build_slot(p->tab, p->st, p->arena, &h[b]))) goto fail;
-    if ((rc = p->arena.alloc(sizeof(SlotDesc) * batch, (void**)&p->d_slots))) goto fail;
-    if ((rc = upload(p->d_slots, h.data(), sizeof(SlotDesc) * batch, p->stream))) goto fail;
+    if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
     if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
     if ((rc = p->arena.alloc(sizeof(double) * p->tab.N * batch, (void**)&p->d_scratch))) goto fail;
   }
@@ -276,7 +290,9 @@ agg_status agg_plan_destroy(agg_plan* p) {
 }
 
 static agg_status run(agg_plan* p, int mode, double dt, double* state, double* outp, bool row) {
-  LaunchArgs a = base_args(p->tab, p->st, p->d_slots, p->batch);
+  LaunchArgs a = base_args(p->tab, p->st, nullptr, p->batch);
+  a.base = p->base;
+  a.stride = p->stride;
   a.mode = mode;
   a.dt = dt;
   a.ext_state = state;

@@ -33,14 +33,16 @@ __device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& 
   e = b - (s - a);
 }
 
+// Dekker's addition: the error terms of the two high parts are kept exactly and
+// the low parts are added once, so |result - (a+b)| <= ~2^-47 (|a| + |b|).
+// That absolute bound is what the normwise error of a transform, a product of
+// spectra and an inverse transform depends on; relative accuracy under
+// cancellation (the IEEE-style double-TwoSum addition) is not needed here.
 __device__ __forceinline__ ff operator+(ff a, ff b) {
 #pragma clang fp contract(off)
-  float s, e, t, f;
+  float s, e;
   two_sum(a.hi, b.hi, s, e);
-  two_sum(a.lo, b.lo, t, f);
-  e += t;
-  fast_two_sum(s, e, s, e);
-  e += f;
+  e += a.lo + b.lo;
   ff r;
   fast_two_sum(s, e, r.hi, r.lo);
   return r;

@@ -195,9 +195,19 @@ void Engine::tick() {
     Request* first = std::get<2>(launches[b]);
     LaunchArgs a = base_args(first->tab, first->st, dd + off, cnt);
     a.mode = -1;
-    int umax = 1;
+    int umax = 1, tpm = 0, tidm = 0;
     for (int i = 0; i < cnt; ++i) umax = std::max(umax, hd[off + i].u);
+    for (auto& kv2 : buckets)
+      for (Request* r : kv2.second)
+        if (r->tab.L == first->tab.L && r->tab.M1 == first->tab.M1 && r->tab.M2 == first->tab.M2 &&
+            r->tab.g == first->tab.g && r->tab.prec == first->tab.prec) {
+          tpm = std::max(tpm, r->st.ntab);
+          tidm = std::max(tidm, r->st.Tp + r->st.Tq);
+        }
     a.umax = umax;
+    a.ub = col_batch(first->tab.prec, first->tab.M1, umax, cnt * (first->tab.M2 / first->tab.g));
+    a.tab_max = tpm;
+    a.coef_max = tidm;
     e = launch_row(first->tab.prec, a, stream);
     if (e == hipSuccess) e = launch_col(first->tab.prec, a, stream);
   }

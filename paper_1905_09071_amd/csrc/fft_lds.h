@@ -1,4 +1,4 @@
-// Batched power-of-two FFTs held in LDS, for one 256-thread workgroup.
+// Batched power-of-two FFTs held in LDS, for one workgroup of NT threads.
 //
 // Stockham autosort formulation: stage s with radix R and span NS (product of
 // the radices before it) takes butterfly b (0 <= b < P/R) from positions
@@ -14,6 +14,23 @@
 namespace agg {
 
 constexpr int kThreads = 256;
+
+// Workgroup barrier that orders LDS only.  Unlike __syncthreads() it does not
+// wait for outstanding global loads and stores, so prefetched global data stays
+// in flight across the LDS-only stages of a transform.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// LDS position of element i of a transform: one pad slot after every 16
+// elements.  Stockham stage writes land at stride R*16 bytes in the first
+// stages, which without padding puts up to 32 lanes of a wave on one bank
+// group; with it every stage stays at the 4-way minimum of 16-byte accesses.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+// padded length of one transform of P elements in LDS
+__host__ __device__ constexpr int lds_len(int P) { return P + (P >> 4); }
 
 // tw[e] = exp(-2 pi i e / P) in the working precision
 template <class T, int DIR>
@@ -70,27 +87,27 @@ template <class T, int R, int DIR> __device__ __forceinline__ void dftR(cplx<T>*
 }
 
 // One Stockham stage over `nfft` transforms (nfft <= NB) stored at stride STR.
-template <class T, int P, int R, int NS, int DIR, int NB, int STR>
+template <class T, int P, int R, int NS, int DIR, int NB, int STR, int NT>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, int nfft, const cplx<T>* __restrict__ tw) {
   constexpr int BPF = P / R;
   constexpr int TOT = NB * BPF;
-  constexpr int K = (TOT + kThreads - 1) / kThreads;
+  constexpr int K = (TOT + NT - 1) / NT;
   const int tid = threadIdx.x;
   const int nvalid = nfft * BPF;
   cplx<T> v[K][R];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    int bg = tid + kk * kThreads;
+    int bg = tid + kk * NT;
     if (bg < nvalid) {
       int f = bg / BPF, b = bg % BPF;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[kk][r] = buf[f * STR + b + r * BPF];
+      for (int r = 0; r < R; ++r) v[kk][r] = buf[f * STR + lds_pad(b + r * BPF)];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    int bg = tid + kk * kThreads;
+    int bg = tid + kk * NT;
     if (bg < nvalid) {
       int f = bg / BPF, b = bg % BPF;
       int j = b % NS;
@@ -104,29 +121,32 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int nfft, const cplx<T>*
       dftR<T, R, DIR>(v[kk]);
       int base = (b / NS) * NS * R + j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[f * STR + base + r * NS] = v[kk][r];
+      for (int r = 0; r < R; ++r) buf[f * STR + lds_pad(base + r * NS)] = v[kk][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-template <class T, int P, int NS, int DIR, int NB, int STR>
+template <class T, int P, int NS, int DIR, int NB, int STR, int NT>
 __device__ __forceinline__ void fft_stages(cplx<T>* buf, int nfft, const cplx<T>* __restrict__ tw) {
   if constexpr (NS < P) {
     constexpr int REM = P / NS;
     constexpr int R = REM >= 8 ? 8 : REM;
-    fft_stage<T, P, R, NS, DIR, NB, STR>(buf, nfft, tw);
-    fft_stages<T, P, NS * R, DIR, NB, STR>(buf, nfft, tw);
+    fft_stage<T, P, R, NS, DIR, NB, STR, NT>(buf, nfft, tw);
+    fft_stages<T, P, NS * R, DIR, NB, STR, NT>(buf, nfft, tw);
   }
 }
 
-// Transforms `count` sequences of length P at stride STR, NB at a time.  Every
-// thread of the block must call this (it synchronises internally).
-template <class T, int P, int DIR, int NB, int STR>
+// Transforms `count` sequences of length P at stride STR (>= lds_len(P)),
+// element i of sequence f at buf[f*STR + lds_pad(i)], NB at a time.  Every
+// thread of the block must call this (it synchronises internally, on LDS only:
+// the caller must have made its LDS input visible with lds_barrier() or
+// __syncthreads() first).
+template <class T, int P, int DIR, int NB, int STR, int NT = kThreads>
 __device__ __forceinline__ void fft_batch(cplx<T>* buf, int count, const cplx<T>* __restrict__ tw) {
   for (int c0 = 0; c0 < count; c0 += NB) {
     int nf = count - c0 < NB ? count - c0 : NB;
-    fft_stages<T, P, 1, DIR, NB, STR>(buf + c0 * STR, nf, tw);
+    fft_stages<T, P, 1, DIR, NB, STR, NT>(buf + c0 * STR, nf, tw);
   }
 }
 

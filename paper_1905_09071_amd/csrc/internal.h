@@ -27,9 +27,9 @@ struct DeviceArena {
 struct SharedTables {
   const PlanTables* tab = nullptr;
   double* cols = nullptr;
-  const int *p_off = nullptr, *p_ids = nullptr, *q_off = nullptr, *q_ids = nullptr, *q_kmode = nullptr;
-  const double *p_coef = nullptr, *q_coef = nullptr;
-  int Tp = 0, Tq = 0;
+  const int* tabs = nullptr;       // int blob (see SlotDesc)
+  const double* coef = nullptr;    // coefficient blob
+  int Tp = 0, Tq = 0, ntab = 0, o_pids = 0, o_qoff = 0, o_qids = 0, o_qkm = 0;
   void *twP1 = nullptr, *twP2 = nullptr, *twLlo = nullptr, *twLhi = nullptr;
 };
 
@@ -44,6 +44,7 @@ hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_row(int prec, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_moments(const double* n, int64_t total, int64_t N, double* part, int nblocks,
                           hipStream_t s);
-size_t row_smem_bytes(int prec, int umax, int M2);
+size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max);
+int col_batch(int prec, int M1, int u, int nworkgroups);
 
 }  // namespace agg

@@ -41,13 +41,11 @@ struct SlotDesc {
   void* V;                // M stored complex values
   double* dots;           // u*ngroups partial dot products (column kernel -> row kernel)
   double* G;              // u loss-term weights of the current evaluation
-  const int* p_off;       // Tp+1 offsets into p_ids
-  const int* p_ids;       // column ids of each gain term
-  const double* p_coef;   // multiplicity / d!
-  const int* q_off;       // Tq+1 offsets into q_ids
-  const int* q_ids;       // ids of modes 1..d-1 of each loss term
-  const int* q_kmode;     // k-mode column id of each loss term
-  const double* q_coef;   // multiplicity / (d-1)!
+  // term tables, one int blob: p_off[Tp+1] | p_ids | q_off[Tq+1] | q_ids | q_kmode[Tq]
+  // (offsets below), and one binary64 blob: p_coef[Tp] (mult/d!) | q_coef[Tq] (mult/(d-1)!)
+  const int* tab;
+  const double* coef;
+  int ntab, o_pids, o_qoff, o_qids, o_qkm;
   int N, u, Tp, Tq;
   int mode;               // per-slot column mode (when the launch mode is < 0)
   int row_on;             // per-slot row pass switch (when the launch mode is < 0)
@@ -55,8 +53,16 @@ struct SlotDesc {
   double* out;            // per-slot RHS output (CM_RHS without external output)
 };
 
+// Byte strides between consecutive slots' buffers when every slot of a launch
+// shares one kernel set and its buffers are carved from batched allocations.
+struct SlotStride {
+  int64_t k1, ntil, Z1, V, dots, G;
+};
+
 struct LaunchArgs {
-  const SlotDesc* slots;
+  const SlotDesc* slots;  // per-slot descriptors in device memory, or nullptr:
+  SlotDesc base;          //   then slot s is base with its buffers moved by s*stride
+  SlotStride stride;
   int nslots;
   int mode;               // >= 0: same mode for all slots; < 0: per slot
   double dt;
@@ -67,8 +73,17 @@ struct LaunchArgs {
   const void* twLlo;      // w_L^a,       a < 2^b
   const void* twLhi;      // w_L^(a 2^b), a < L/2^b
   int M1, M2, g, b;
+  int lgg;                // log2(g)
   int64_t L;
   int umax;               // largest u among the slots (row kernel LDS sizing)
+  int ub;                 // forward columns transformed together in the column pass
+  int tab_max;            // largest term-table int blob among the slots
+  int coef_max;           // largest coefficient blob (Tp + Tq) among the slots
 };
+
+constexpr int kColBatch = 4;             // upper bound of LaunchArgs::ub
+constexpr int kColThreads = 512;         // threads of a column-pass workgroup
+constexpr int kColPrefetch = 4;          // factor columns held in registers by the column pass
+constexpr int kColLdsBudget = 120 * 1024; // LDS the column pass may use
 
 }  // namespace agg

@@ -28,23 +28,70 @@ __device__ __forceinline__ cplx<T> twL(const LaunchArgs& a, int64_t e) {
   return cmul(hi[e >> a.b], lo[e & mask]);
 }
 
+// Sum over the 64 lanes of a wavefront (xor butterfly: every lane ends with the
+// same value, fixed order, so the result is reproducible).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Descriptor of one slot: from device memory, or built from the launch's base
+// descriptor and strides (no dependent load before the first data request).
+__device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
+  if (a.slots) return a.slots[slot];
+  SlotDesc sd = a.base;
+  sd.k1 = (double*)((char*)sd.k1 + slot * a.stride.k1);
+  sd.ntil = (double*)((char*)sd.ntil + slot * a.stride.ntil);
+  sd.Z1 = (void*)((char*)sd.Z1 + slot * a.stride.Z1);
+  sd.V = (void*)((char*)sd.V + slot * a.stride.V);
+  sd.dots = (double*)((char*)sd.dots + slot * a.stride.dots);
+  sd.G = (double*)((char*)sd.G + slot * a.stride.G);
+  return sd;
+}
+
+// Block index -> work index such that consecutive work indices run on the same
+// XCD (workgroups are dealt round-robin over the 8 XCDs), so neighbouring
+// column groups share one L2 and its cache lines are written whole.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
+template <class T, int NUM>
+__device__ __forceinline__ void load_table(cplx<T>* dst, const void* src) {
+  const cplx<T>* s = (const cplx<T>*)src;
+#pragma unroll
+  for (int i = threadIdx.x; i < NUM; i += kThreads) dst[i] = s[i];
+}
+
 // ---------------------------------------------------------------------------
 // Column pass.  Work item = (slot, group of g adjacent columns j2).
+// LDS: the M1 twiddles, then up to ub*g columns of M1 values.
+// Every global value the pass needs (the combined spectrum's columns, the
+// state and Heun vectors, the first kColPrefetch factor columns and the
+// four-step twiddles) is requested in one round at the start, so a launch
+// costs about three memory round trips: descriptor, data, stores.
 // ---------------------------------------------------------------------------
 template <class T, int M1>
-__global__ __launch_bounds__(kThreads) void col_kernel(LaunchArgs a) {
-  constexpr int GMAX = (2048 / M1) > 0 ? 2048 / M1 : 1;
-  constexpr int STR = M1;
+__global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
+  constexpr int NT = kColThreads;
+  constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
+  constexpr int STR = lds_len(M1);
   constexpr int CAP = GMAX * M1;
-  constexpr int IPT = (CAP + kThreads - 1) / kThreads;
-  __shared__ cplx<T> buf[CAP];
-  __shared__ double red[kThreads];
+  constexpr int IPT = (CAP + NT - 1) / NT;
+  constexpr int NWAVE = NT / 64;
+  constexpr int UP = kColPrefetch;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* tw = (cplx<T>*)smem;
+  cplx<T>* buf = tw + M1;
+  __shared__ double red[NWAVE][kColBatch];
 
-  const int M2 = a.M2, g = a.g;
-  const int ngroups = M2 / g;
-  const int slot = blockIdx.x / ngroups;
-  const int grp = blockIdx.x - slot * ngroups;
-  const SlotDesc sd = a.slots[slot];
+  const int M2 = a.M2, g = a.g, lgg = a.lgg;
+  const int ngroups = M2 >> lgg;
+  const int w = xcd_contiguous(blockIdx.x, a.nslots * ngroups);
+  const int slot = w / ngroups;
+  const int grp = w - slot * ngroups;
+  const SlotDesc sd = slot_desc(a, slot);
   const int mode = a.mode >= 0 ? a.mode : sd.mode;
   if (mode == CM_NONE) return;
   const double dt = a.mode >= 0 ? a.dt : sd.dt;
@@ -52,57 +99,112 @@ __global__ __launch_bounds__(kThreads) void col_kernel(LaunchArgs a) {
   const int64_t M = (int64_t)M1 * M2;
   const int j2_0 = grp * g;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int nitems = g * M1;
+  const int u = sd.u;
+  const bool inv = mode_has_inverse(mode), fwd = mode_has_forward(mode);
+  const bool stage2 = (mode == CM_H2 || mode == CM_H2_FWD);
   double* state = a.ext_state ? a.ext_state + (size_t)slot * N : sd.n_state;
-  const cplx<T>* twP1 = (const cplx<T>*)a.twP1;
+  const double* ev = stage2 ? sd.ntil : state;   // state at which f is taken
 
-  double s0[IPT], s1[IPT];   // new state at sizes 2j and 2j+1 of each item
-
-  if (mode_has_inverse(mode)) {
+  // ---- one round of global requests ----
+  load_table<T, M1>(tw, a.twP1);
+  int64_t pos[IPT];          // size 2j of each item (2j+1 is the odd partner)
+  double pe[IPT][2], pn[IPT][2], pk[IPT][2], uc[UP][IPT][2];
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    int idx = tid + it * NT;
+    int j1 = idx >> lgg, jl = idx & (g - 1);
+    pos[it] = idx < nitems ? 2 * (j2_0 + jl + (int64_t)M2 * j1) : N + 1;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      int64_t s = pos[it] + e;
+      bool ok = s >= 1 && s <= N;
+      pe[it][e] = ok ? ev[s - 1] : 0.0;
+      pn[it][e] = (ok && stage2) ? state[s - 1] : 0.0;
+      pk[it][e] = (ok && stage2) ? sd.k1[s - 1] : 0.0;
+#pragma unroll
+      for (int q = 0; q < UP; ++q) uc[q][it][e] = (ok && q < u) ? sd.cols[(size_t)q * N + (s - 1)] : 0.0;
+    }
+  }
+  cplx<T> wst[IPT];          // four-step twiddles w_M^(j2 k1), shared by all columns
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    int idx = tid + it * NT;
+    int k1 = idx >> lgg, jl = idx & (g - 1);
+    int64_t e = (2 * (int64_t)(j2_0 + jl) * k1) & (a.L - 1);
+    wst[it] = (fwd && idx < nitems) ? twL<T>(a, e) : czero<T>();
+  }
+  if (inv) {
     const cplx<T>* V = (const cplx<T>*)sd.V;
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
-      int idx = tid + it * kThreads;
+      int idx = tid + it * NT;
       if (idx < nitems) {
-        int k1 = idx / g, jl = idx - k1 * g;
-        buf[jl * STR + k1] = V[(int64_t)k1 * M2 + j2_0 + jl];
+        int k1 = idx >> lgg, jl = idx & (g - 1);
+        buf[jl * STR + lds_pad(k1)] = V[(int64_t)k1 * M2 + j2_0 + jl];
       }
     }
-    __syncthreads();
-    fft_batch<T, M1, +1, GMAX, STR>(buf, g, twP1);
+  }
+
+  double s0[IPT], s1[IPT];   // state the forward pass weights, at sizes 2j, 2j+1
+  if (inv) {
+    lds_barrier();
+    fft_batch<T, M1, +1, GMAX, STR, NT>(buf, g, tw);
+
+    // loss weight g_k = sum_c U_c(k) G_c
+    double gk[IPT][2];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) gk[it][0] = gk[it][1] = 0.0;
+#pragma unroll
+    for (int q = 0; q < UP; ++q) {
+      if (q < u) {
+        const double Gc = sd.G[q];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+          gk[it][0] += uc[q][it][0] * Gc;
+          gk[it][1] += uc[q][it][1] * Gc;
+        }
+      }
+    }
+    for (int c = UP; c < u; ++c) {
+      const double Gc = sd.G[c];
+      const double* col = sd.cols + (size_t)c * N;
+#pragma unroll
+      for (int it = 0; it < IPT; ++it)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          int64_t s = pos[it] + e;
+          if (s >= 1 && s <= N) gk[it][e] += col[s - 1] * Gc;
+        }
+    }
 
     const double invL = 1.0 / (double)a.L;
-    const bool stage2 = (mode == CM_H2 || mode == CM_H2_FWD);
-    const double* ev = stage2 ? sd.ntil : state;   // state at which f is taken
     double* out = a.ext_out ? a.ext_out + (size_t)slot * N : sd.out;
-    const int u = sd.u;
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
-      int idx = tid + it * kThreads;
+      int idx = tid + it * NT;
       s0[it] = 0.0;
       s1[it] = 0.0;
       if (idx < nitems) {
-        int j1 = idx / g, jl = idx - j1 * g;
-        int64_t j = j2_0 + jl + (int64_t)M2 * j1;
-        cplx<T> w = buf[jl * STR + j1];
-        double y[2] = {Real<T>::to_d(w.re), Real<T>::to_d(w.im)};
+        int j1 = idx >> lgg, jl = idx & (g - 1);
+        cplx<T> wv = buf[jl * STR + lds_pad(j1)];
+        double y[2] = {Real<T>::to_d(wv.re), Real<T>::to_d(wv.im)};
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-          int64_t s = 2 * j + e;
+          int64_t s = pos[it] + e;
           double val = 0.0;
           if (s >= 1 && s <= N) {
             double p = s >= 2 ? y[e] * invL : 0.0;
-            double gk = 0.0;
-            for (int c = 0; c < u; ++c) gk += sd.cols[(size_t)c * N + (s - 1)] * sd.G[c];
-            double f = p - ev[s - 1] * gk;
+            double f = p - pe[it][e] * gk[it][e];
             if (mode == CM_RHS) {
               out[s - 1] = f;
             } else if (mode == CM_H1) {
               sd.k1[s - 1] = f;
-              val = state[s - 1] + dt * f;
+              val = pe[it][e] + dt * f;
               sd.ntil[s - 1] = val;
             } else {
-              val = state[s - 1] + 0.5 * dt * (sd.k1[s - 1] + f);
+              val = pn[it][e] + 0.5 * dt * (pk[it][e] + f);
               state[s - 1] = val;
             }
           }
@@ -110,126 +212,168 @@ __global__ __launch_bounds__(kThreads) void col_kernel(LaunchArgs a) {
         }
       }
     }
-    __syncthreads();
+    if (!fwd) return;
+    lds_barrier();
   } else {
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
-      int idx = tid + it * kThreads;
-      s0[it] = 0.0;
-      s1[it] = 0.0;
-      if (idx < nitems) {
-        int j1 = idx / g, jl = idx - j1 * g;
-        int64_t j = j2_0 + jl + (int64_t)M2 * j1;
-        if (2 * j >= 1 && 2 * j <= N) s0[it] = state[2 * j - 1];
-        if (2 * j + 1 <= N) s1[it] = state[2 * j];
-      }
+      s0[it] = pe[it][0];
+      s1[it] = pe[it][1];
     }
   }
 
-  if (!mode_has_forward(mode)) return;
   cplx<T>* Z1 = (cplx<T>*)sd.Z1;
-  for (int c = 0; c < sd.u; ++c) {
-    const double* col = sd.cols + (size_t)c * N;
-    double dsum = 0.0;
+  for (int cb = 0; cb < u; cb += a.ub) {
+    const int nc = u - cb < a.ub ? u - cb : a.ub;
+    // weighted columns x_c = U_c * state for c in [cb, cb+nc)
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-      int idx = tid + it * kThreads;
-      if (idx < nitems) {
-        int j1 = idx / g, jl = idx - j1 * g;
-        int64_t j = j2_0 + jl + (int64_t)M2 * j1;
-        double x0 = (2 * j >= 1 && 2 * j <= N) ? col[2 * j - 1] * s0[it] : 0.0;
-        double x1 = (2 * j + 1 <= N) ? col[2 * j] * s1[it] : 0.0;
-        buf[jl * STR + j1] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
-        dsum += x0 + x1;
+    for (int q = 0; q < UP; ++q) {
+      if (q >= cb && q < cb + nc) {
+        double dsum = 0.0;
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+          int idx = tid + it * NT;
+          if (idx < nitems) {
+            int j1 = idx >> lgg, jl = idx & (g - 1);
+            double x0 = uc[q][it][0] * s0[it];
+            double x1 = uc[q][it][1] * s1[it];
+            buf[((q - cb) * g + jl) * STR + lds_pad(j1)] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
+            dsum += x0 + x1;
+          }
+        }
+        dsum = wave_sum(dsum);
+        if (lane == 0) red[wave][q - cb] = dsum;
       }
     }
-    __syncthreads();
-    fft_batch<T, M1, -1, GMAX, STR>(buf, g, twP1);
+    for (int c = cb > UP ? cb : UP; c < cb + nc; ++c) {
+      const double* col = sd.cols + (size_t)c * N;
+      double dsum = 0.0;
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-      int idx = tid + it * kThreads;
-      if (idx < nitems) {
-        int k1 = idx / g, jl = idx - k1 * g;
-        int j2 = j2_0 + jl;
-        int64_t e = (2 * (int64_t)j2 * k1) & (a.L - 1);
-        Z1[(size_t)c * M + (int64_t)k1 * M2 + j2] = cmul(buf[jl * STR + k1], twL<T>(a, e));
+      for (int it = 0; it < IPT; ++it) {
+        int idx = tid + it * NT;
+        if (idx < nitems) {
+          int j1 = idx >> lgg, jl = idx & (g - 1);
+          int64_t s = pos[it];
+          double x0 = (s >= 1 && s <= N) ? col[s - 1] * s0[it] : 0.0;
+          double x1 = (s + 1 <= N) ? col[s] * s1[it] : 0.0;
+          buf[((c - cb) * g + jl) * STR + lds_pad(j1)] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
+          dsum += x0 + x1;
+        }
+      }
+      dsum = wave_sum(dsum);
+      if (lane == 0) red[wave][c - cb] = dsum;
+    }
+    lds_barrier();
+    fft_batch<T, M1, -1, GMAX * kColBatch, STR, NT>(buf, nc * g, tw);
+    for (int q = 0; q < nc; ++q) {
+#pragma unroll
+      for (int it = 0; it < IPT; ++it) {
+        int idx = tid + it * NT;
+        if (idx < nitems) {
+          int k1 = idx >> lgg, jl = idx & (g - 1);
+          Z1[(size_t)(cb + q) * M + (int64_t)k1 * M2 + j2_0 + jl] =
+              cmul(buf[(q * g + jl) * STR + lds_pad(k1)], wst[it]);
+        }
       }
     }
-    red[tid] = dsum;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    if (tid < nc) {
+      double t = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < NWAVE; ++wv) t += red[wv][tid];
+      sd.dots[(size_t)(cb + tid) * ngroups + grp] = t;
     }
-    if (tid == 0) sd.dots[(size_t)c * ngroups + grp] = red[0];
+    lds_barrier();
   }
 }
 
 // ---------------------------------------------------------------------------
 // Row pass.  Work item = (slot, k1 in [0, M1/2]) covering rows k1 and M1-k1.
+// LDS: M2 twiddles (global for M2 = 2048, where the rows need the room), the
+// gain-term tables, u*nrows rows, u Nyquist values.
 // ---------------------------------------------------------------------------
 template <class T, int M2>
 __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
+  constexpr bool TW_LDS = M2 <= 512;
   constexpr int NB = (2048 / M2) > 0 ? 2048 / M2 : 1;
-  constexpr int STR = M2;
+  constexpr int STR = lds_len(M2);
+  constexpr int NWAVE = kThreads / 64;
+  constexpr int UPT = (M2 + kThreads - 1) / kThreads;       // combine units per thread
+  constexpr int VPT = (2 * M2 + kThreads - 1) / kThreads;   // output values per thread
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[kThreads];
 
   const int M1 = a.M1;
   const int nwork = M1 / 2 + 1;
   const int slot = blockIdx.x / nwork;
   const int k1 = blockIdx.x - slot * nwork;
-  const SlotDesc sd = a.slots[slot];
+  const SlotDesc sd = slot_desc(a, slot);
   const int row_on = a.mode >= 0 ? 1 : sd.row_on;
   if (!row_on) return;
   const int u = sd.u;
   const int64_t M = (int64_t)M1 * M2;
   const int tid = threadIdx.x;
-  cplx<T>* X = (cplx<T>*)smem;                         // u * nrows rows
-  cplx<T>* nyq = X + (size_t)a.umax * 2 * STR;         // u Nyquist values (bin k = M)
-  double* sdot = (double*)(nyq + a.umax);              // u dot products
+  const int lane = tid & 63, wave = tid >> 6;
 
-  // loss-term weights of this evaluation, from the column pass's partial dots
-  if (k1 == 0) {
-    const int ngroups = M2 / a.g;
-    for (int c = 0; c < u; ++c) {
-      double s = 0.0;
-      for (int q = tid; q < ngroups; q += kThreads) s += sd.dots[(size_t)c * ngroups + q];
-      red[tid] = s;
-      __syncthreads();
-      for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-      }
-      if (tid == 0) sdot[c] = red[0];
-      __syncthreads();
-    }
-    if (tid == 0) {
-      for (int c = 0; c < u; ++c) sd.G[c] = 0.0;
-      for (int t = 0; t < sd.Tq; ++t) {
-        double pr = sd.q_coef[t];
-        for (int o = sd.q_off[t]; o < sd.q_off[t + 1]; ++o) pr *= sdot[sd.q_ids[o]];
-        sd.G[sd.q_kmode[t]] += pr;
-      }
-    }
-  }
+  // LDS layout
+  cplx<T>* twl = (cplx<T>*)smem;                         // M2 when TW_LDS
+  const cplx<T>* tw = TW_LDS ? twl : (const cplx<T>*)a.twP2;
+  cplx<T>* X = twl + (TW_LDS ? M2 : 0);                  // umax*2 rows
+  cplx<T>* nyq = X + (size_t)a.umax * 2 * STR;           // umax
+  double* coef = (double*)(nyq + a.umax);                // coef_max
+  double* red = coef + a.coef_max;                       // NWAVE * umax
+  double* sdot = red + NWAVE * a.umax;                   // umax
+  int* tab = (int*)(sdot + a.umax);                      // tab_max
 
   const int nrows = (k1 == 0 || 2 * k1 == M1) ? 1 : 2;
   const int rows[2] = {k1, M1 - k1};
+  const int Tp = sd.Tp;
+
+  // everything this work item reads from HBM is requested up front
+  if (TW_LDS) load_table<T, M2>(twl, a.twP2);
+  for (int i = tid; i < sd.ntab; i += kThreads) tab[i] = sd.tab[i];
+  for (int i = tid; i < Tp + sd.Tq; i += kThreads) coef[i] = sd.coef[i];
   const cplx<T>* Z1 = (const cplx<T>*)sd.Z1;
   const int nload = u * nrows * M2;
+#pragma unroll 8
   for (int idx = tid; idx < nload; idx += kThreads) {
     int cr = idx / M2, k2 = idx - cr * M2;
     int c = cr / nrows, rr = cr - c * nrows;
-    X[cr * STR + k2] = Z1[(size_t)c * M + (int64_t)rows[rr] * M2 + k2];
+    X[cr * STR + lds_pad(k2)] = Z1[(size_t)c * M + (int64_t)rows[rr] * M2 + k2];
   }
-  __syncthreads();
-  fft_batch<T, M2, -1, NB, STR>(X, u * nrows, (const cplx<T>*)a.twP2);
+  const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
+  cplx<T> wku[UPT];   // w_L^k of this thread's combine units
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) {
+    int unit = tid + i * kThreads;
+    wku[i] = unit < nunits ? twL<T>(a, k1 + (int64_t)M1 * unit) : czero<T>();
+  }
+  cplx<T> wvo[VPT];   // w_M^(-j2 row) of this thread's outputs (conjugated at use)
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    int idx = tid + i * kThreads;
+    int rr = idx / M2, j2 = idx - rr * M2;
+    int64_t e = (2 * (int64_t)j2 * rows[rr < 2 ? rr : 0]) & (a.L - 1);
+    wvo[i] = idx < nrows * M2 ? twL<T>(a, e) : czero<T>();
+  }
+  if (k1 == 0) {   // partial dots of the column pass -> per-wave sums
+    const int ngroups = M2 / a.g;
+    for (int c = 0; c < u; ++c) {
+      double sacc = 0.0;
+      for (int q = tid; q < ngroups; q += kThreads) sacc += sd.dots[(size_t)c * ngroups + q];
+      sacc = wave_sum(sacc);
+      if (lane == 0) red[wave * a.umax + c] = sacc;
+    }
+  }
+  lds_barrier();
+  fft_batch<T, M2, -1, NB, STR>(X, u * nrows, tw);
 
   // bins k = k1 + M1*iA and M - k, spectra of the real inputs, their weighted
   // products, and the even/odd packing of the real inverse
-  const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
-  for (int unit = tid; unit < nunits; unit += kThreads) {
+  const int* poff = tab;
+  const int* pids = tab + sd.o_pids;
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) {
+    const int unit = tid + i * kThreads;
+    if (unit >= nunits) continue;
     const int iA = unit;
     int iB, rB;
     if (k1 == 0) { iB = (M2 - iA) & (M2 - 1); rB = 0; }
@@ -237,11 +381,10 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
     else { iB = M2 - 1 - iA; rB = 1; }
     const bool zero_bin = (k1 == 0 && iA == 0);
     const bool self = (rB == 0 && iB == iA);
-    const int64_t kA = k1 + (int64_t)M1 * iA;
-    const cplx<T> wk = twL<T>(a, kA);
+    const cplx<T> wk = wku[i];
     for (int c = 0; c < u; ++c) {
-      cplx<T>* pA = &X[(c * nrows) * STR + iA];
-      cplx<T>* pB = &X[(c * nrows + rB) * STR + iB];
+      cplx<T>* pA = &X[(c * nrows) * STR + lds_pad(iA)];
+      cplx<T>* pB = &X[(c * nrows + rB) * STR + lds_pad(iB)];
       cplx<T> ZA = *pA, ZB = *pB;
       if (zero_bin) {
         *pA = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
@@ -257,13 +400,12 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
       }
     }
     cplx<T> YA = czero<T>(), YB = czero<T>();
-    for (int t = 0; t < sd.Tp; ++t) {
-      T cf = Real<T>::from_d(sd.p_coef[t]);
-      cplx<T> PA = cplx<T>{cf, Real<T>::zero()}, PB = PA;
-      for (int o = sd.p_off[t]; o < sd.p_off[t + 1]; ++o) {
-        int c = sd.p_ids[o];
-        PA = cmul(PA, X[(c * nrows) * STR + iA]);
-        PB = cmul(PB, zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + iB]);
+    for (int t = 0; t < Tp; ++t) {
+      cplx<T> PA = cplx<T>{Real<T>::from_d(coef[t]), Real<T>::zero()}, PB = PA;
+      for (int o = poff[t]; o < poff[t + 1]; ++o) {
+        int c = pids[o];
+        PA = cmul(PA, X[(c * nrows) * STR + lds_pad(iA)]);
+        PB = cmul(PB, zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)]);
       }
       YA = cadd(YA, PA);
       YB = cadd(YB, PB);
@@ -273,19 +415,45 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
     } else {
       cplx<T> F = cadd(YA, cconj(YB));
       cplx<T> Gd = csub(YA, cconj(YB));
-      X[iA] = cadd(F, cmul_i(cmulc(Gd, wk)));
-      if (!self) X[rB * STR + iB] = cadd(cconj(F), cmul_i(cmul(wk, cconj(Gd))));
+      X[lds_pad(iA)] = cadd(F, cmul_i(cmulc(Gd, wk)));
+      if (!self) X[rB * STR + lds_pad(iB)] = cadd(cconj(F), cmul_i(cmul(wk, cconj(Gd))));
     }
   }
-  __syncthreads();
-  fft_batch<T, M2, +1, NB, STR>(X, nrows, (const cplx<T>*)a.twP2);
+  lds_barrier();
+  fft_batch<T, M2, +1, NB, STR>(X, nrows, tw);
 
   cplx<T>* V = (cplx<T>*)sd.V;
-  for (int idx = tid; idx < nrows * M2; idx += kThreads) {
-    int rr = idx / M2, j2 = idx - rr * M2;
-    int64_t row = rows[rr];
-    int64_t e = (2 * (int64_t)j2 * row) & (a.L - 1);
-    V[row * M2 + j2] = cmulc(X[rr * STR + j2], twL<T>(a, e));
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    int idx = tid + i * kThreads;
+    if (idx < nrows * M2) {
+      int rr = idx / M2, j2 = idx - rr * M2;
+      V[(int64_t)rows[rr] * M2 + j2] = cmulc(X[rr * STR + lds_pad(j2)], wvo[i]);
+    }
+  }
+
+  // loss-term weights of this evaluation: G_c = sum over loss terms with k-mode c
+  // of coef * prod of the other modes' dot products
+  if (k1 == 0) {
+    if (tid < u) {
+      double t = 0.0;
+      for (int wv = 0; wv < NWAVE; ++wv) t += red[wv * a.umax + tid];
+      sdot[tid] = t;
+    }
+    lds_barrier();
+    if (tid < u) {
+      const int* qoff = tab + sd.o_qoff;
+      const int* qids = tab + sd.o_qids;
+      const int* qkm = tab + sd.o_qkm;
+      double Gc = 0.0;
+      for (int t = 0; t < sd.Tq; ++t) {
+        if (qkm[t] != tid) continue;
+        double pr = coef[Tp + t];
+        for (int o = qoff[t]; o < qoff[t + 1]; ++o) pr *= sdot[qids[o]];
+        Gc += pr;
+      }
+      sd.G[tid] = Gc;
+    }
   }
 }
 
@@ -322,8 +490,17 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(const double* n, int6
 // ---------------------------------------------------------------------------
 template <class T, int M1>
 static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
+  static bool attr_done = false;   // raise the dynamic LDS cap once per instantiation
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void*)col_kernel<T, M1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kColLdsBudget + 16384);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
+  size_t smem = ((size_t)M1 + (size_t)a.ub * GMAX * lds_len(M1)) * sizeof(cplx<T>);
   dim3 grid(a.nslots * (a.M2 / a.g));
-  hipLaunchKernelGGL((col_kernel<T, M1>), grid, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((col_kernel<T, M1>), grid, dim3(kColThreads), smem, s, a);
   return hipGetLastError();
 }
 
@@ -344,9 +521,24 @@ static hipError_t launch_col_p(const LaunchArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-size_t row_smem_bytes(int prec, int umax, int M2) {
+size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max) {
   size_t cs = prec == 1 ? 8 : 16;
-  return (size_t)umax * 2 * M2 * cs + (size_t)umax * cs + (size_t)umax * 8;
+  return (size_t)(M2 <= 512 ? M2 : 0) * cs + (size_t)umax * 2 * lds_len(M2) * cs + (size_t)umax * cs +
+         (size_t)coef_max * 8 + (size_t)(kThreads / 64 + 1) * umax * 8 + (size_t)tab_max * 4 + 16;
+}
+
+int col_batch(int prec, int M1, int u, int nworkgroups) {
+  size_t cs = prec == 1 ? 8 : 16;
+  size_t gmax = 1024 / M1 > 0 ? 1024 / M1 : 1;
+  size_t per = gmax * lds_len(M1) * cs;
+  long ub = ((long)kColLdsBudget - (long)(M1 * cs)) / (long)per;
+  if (ub < 1) ub = 1;
+  if (ub > kColBatch) ub = kColBatch;
+  if (ub > u) ub = u < 1 ? 1 : u;
+  // a launch that already fills the GPU gains more from occupancy (small LDS
+  // per workgroup) than from transforming several columns per workgroup
+  if (nworkgroups >= 512) ub = 1;
+  return (int)ub;
 }
 
 template <class T, int M2>
@@ -388,7 +580,7 @@ hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_row(int prec, const LaunchArgs& a, hipStream_t s) {
-  size_t smem = row_smem_bytes(prec, a.umax, a.M2);
+  size_t smem = row_smem_bytes(prec, a.umax, a.M2, a.tab_max, a.coef_max);
   if (prec == 0) return launch_row_p<double>(a, s, smem);
   if (prec == 1) return launch_row_p<float>(a, s, smem);
   return launch_row_p<ff>(a, s, smem);

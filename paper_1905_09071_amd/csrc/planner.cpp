@@ -8,7 +8,7 @@
 //    sorted ids of the other modes), merged with integer multiplicities;
 //  - two-pass split M = M1*M2 of the half-length complex transform with the
 //    row working set u*2*M2 complex values capped at 64 KiB while M1 <= 2048;
-//  - column tile g = min(M2, max(1, 2048/M1)).
+//  - column tile g = min(M2, max(1, 1024/M1)).
 #include "planner.h"
 
 #include <algorithm>
@@ -125,7 +125,7 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
     return AGG_EUNSUPPORTED;
   }
   P.M1 = (int)M1; P.M2 = (int)M2;
-  P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 2048 / M1));
+  P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1));
   P.b = (ilog2(L) + 1) / 2;
 
   P.flat = {L, M1, M2, P.g, P.u, (int64_t)P.p_ids.size(), (int64_t)P.q_ids.size(), De};

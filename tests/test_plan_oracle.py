@@ -12,7 +12,7 @@ def test_ballistic_d4_tables():
     then i^-a (id 1); d=3 mode 1 first meets the all-ones column (id 2).
     Gain: d=2 -> {0,1} x2; d=3 -> {0,1,2} x6; d=4 -> {0,1,2,2} x12."""
     t = plan_tables(4, 65536, synth.kernel_ballistic(4, 65536, 0.4), "fp64")
-    assert (t["L"], t["M1"], t["M2"], t["g"], t["u"], t["De"]) == (1 << 18, 512, 256, 4, 3, 4)
+    assert (t["L"], t["M1"], t["M2"], t["g"], t["u"], t["De"]) == (1 << 18, 512, 256, 2, 3, 4)
     assert t["pterms"] == [((0, 1), 2), ((0, 1, 2), 6), ((0, 1, 2, 2), 12)]
     assert t["qterms"] == [((2, 0, (1,)), 1), ((2, 1, (0,)), 1),
                            ((3, 0, (1, 2)), 2), ((3, 1, (0, 2)), 2), ((3, 2, (0, 1)), 2),
