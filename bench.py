@@ -150,6 +150,16 @@ def main():
         plan.close()
         del n
 
+    # the plain fp64 reference evaluation (term by term, unshared, unfused)
+    plan = agg.Plan(D, N, c["kernel"], "fp64", plain=True)
+    n = torch.tensor(c["n0"], dtype=torch.float64, device="cuda:0")
+    psteps = max(5, args.steps // 20)
+    t_plain, _ = time_steps(plan, n, dt, psteps, 2, torch)
+    plain_rate = 2 * psteps / t_plain
+    log(f"[bench] plain fp64: {psteps} steps in {t_plain*1e3:.2f} ms -> {plain_rate:.1f} RHS/s")
+    plan.close()
+    del n
+
     prim = results[args.prec]
     cs = PREC_BYTES[args.prec]
     # dominant kernel of a time step: the pass with the largest device time
@@ -193,6 +203,8 @@ def main():
                    "L": L, "M1": M1, "M2": M2, "parallelism": "single GPU"},
         "rhs_per_s": {p: round(r["rhs_per_s"], 2) for p, r in results.items()},
         "ratio_fp32c_vs_fp64": round(results["fp32c"]["rhs_per_s"] / results["fp64"]["rhs_per_s"], 4),
+        "plain_fp64_rhs_per_s": round(plain_rate, 2),
+        "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -52,8 +52,14 @@ enum {
 };
 
 /* Arithmetic of the spectral path.  AGG_FP32C carries float-float (hi+lo)
- * pairs through every FFT pass, twiddle and product (error-free transforms). */
+ * pairs through every FFT pass, twiddle and product (error-free transforms).
+ * AGG_PLAIN may be OR-ed into the precision of agg_plan_create: the plan then
+ * evaluates the right-hand side term by term, one rank-one term (d, r) at a
+ * time with its own d transforms (no column shared, not even equal ones),
+ * accumulating f, with separate forward, row, inverse and Heun launches per
+ * stage: the unshared, unfused reference evaluation. */
 typedef enum { AGG_FP64 = 0, AGG_FP32 = 1, AGG_FP32C = 2 } agg_precision;
+#define AGG_PLAIN 0x100
 
 /* One collision order d: C^(d) = sum_r prod_m U_m(i_m, r).
  * U[m-1] is a HOST pointer to N*rank doubles, column-major by rank:
@@ -73,6 +79,7 @@ typedef struct agg_plan agg_plan;
  * into plan-owned device memory: the caller may free them on return.
  * hip_stream: a hipStream_t (NULL = the null stream) on which every later call
  * of this plan is enqueued.
+ * prec may carry the AGG_PLAIN option bit.
  * Errors: AGG_EINVAL (D outside [2, AGG_MAX_D], N < 1, bad/duplicate d, rank < 0,
  * NULL factor with rank > 0, batch < 1, unknown precision, out == NULL),
  * AGG_ENONFINITE (a non-finite factor), AGG_EUNSUPPORTED (transform length

@@ -9,7 +9,8 @@ P2  FFT length: L = max(16, smallest power of two >= De*N - 1).  A cyclic
     the half-length transform that carries a real length-L transform.
 P3  Column ids: scan d = 2..D ascending, m = 1..d, r = 1..R_d; the column
     U^(d)_m(:, r) gets the id of the first earlier column that is bitwise equal
-    (all N binary64 words), else the next new id.  u = number of ids.
+    (all N binary64 words), else the next new id.  u = number of ids.  Without
+    sharing (the plain reference evaluation) every column gets a new id.
 P4  Gain terms: for each (d, r) the key is the ascending-sorted tuple of the d
     column ids; equal keys merge and count a multiplicity.  Order: by d, then
     lexicographic key.  Coefficient = multiplicity / d!.
@@ -44,7 +45,7 @@ def _log2_exact(x: int) -> int:
     return x.bit_length() - 1
 
 
-def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64"):
+def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = True):
     ranks = {d: (kernel[d].shape[1] if d in kernel else 0) for d in range(2, D + 1)}
     De = max([d for d in range(2, D + 1) if ranks[d] > 0], default=2)
     L = 1
@@ -62,7 +63,7 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64"):
                 key = np.ascontiguousarray(kernel[d][m, r], dtype=np.float64).tobytes()
                 found = -1
                 for j, kk in enumerate(ids):
-                    if kk == key:
+                    if dedup and kk == key:
                         found = j
                         break
                 if found < 0:

@@ -36,13 +36,17 @@ def make_terms(D: int, N: int, kernel: dict):
     return arr, len(items), keep
 
 
-def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64") -> np.ndarray:
+AGG_PLAIN = 0x100
+
+
+def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", plain: bool = False) -> np.ndarray:
     """The planner's integer tables (host only, no device touched)."""
     terms, nt, keep = make_terms(D, N, kernel)
     ln = ctypes.c_int64(0)
-    lib().agg_plan_tables(D, N, terms, nt, PREC[prec], None, 0, ctypes.byref(ln))
+    code = PREC[prec] | (AGG_PLAIN if plain else 0)
+    lib().agg_plan_tables(D, N, terms, nt, code, None, 0, ctypes.byref(ln))
     out = np.zeros(max(ln.value, 1), dtype=np.int64)
-    check(lib().agg_plan_tables(D, N, terms, nt, PREC[prec],
+    check(lib().agg_plan_tables(D, N, terms, nt, code,
                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.size, ctypes.byref(ln)))
     del keep
     return out[:ln.value]
@@ -73,12 +77,15 @@ def _check_state(t, numel):
 class Plan:
     """agg_plan: a kernel set, precision and batch size bound to a stream."""
 
-    def __init__(self, D: int, N: int, kernel: dict, prec: str = "fp64", batch: int = 1, stream=None):
-        self.D, self.N, self.batch, self.prec = D, N, batch, prec
+    def __init__(self, D: int, N: int, kernel: dict, prec: str = "fp64", batch: int = 1, stream=None,
+                 plain: bool = False):
+        """plain=True: the term-by-term, unshared, unfused reference evaluation."""
+        self.D, self.N, self.batch, self.prec, self.plain = D, N, batch, prec, plain
         terms, nt, keep = make_terms(D, N, kernel)
         self._stream = stream
         h = ctypes.c_void_p()
-        check(lib().agg_plan_create(D, N, terms, nt, PREC[prec], batch, _stream_handle(stream),
+        code = PREC[prec] | (AGG_PLAIN if plain else 0)
+        check(lib().agg_plan_create(D, N, terms, nt, code, batch, _stream_handle(stream),
                                     ctypes.byref(h)))
         del keep
         self._h = h

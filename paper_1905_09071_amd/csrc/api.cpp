@@ -230,6 +230,10 @@ struct agg_plan {
   double* d_scratch = nullptr;  // batch*N doubles: output of timed inverse passes
   int moment_blocks = 64;
   bool trivial = false;       // no term with rank > 0: f == 0
+  // AGG_PLAIN: one sub-plan per rank-one term, and the Heun vectors of the batch
+  bool plain = false;
+  std::vector<agg_plan*> subs;
+  double *k1p = nullptr, *k2p = nullptr, *ntp = nullptr;
 };
 
 extern "C" {
@@ -246,7 +250,9 @@ agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t 
                            agg_precision prec, int64_t* out, int64_t cap, int64_t* len) {
   PlanTables T;
   std::string err;
-  agg_status rc = plan_build(D, N, terms, nterms, prec, &T, &err);
+  const int opt = (int)prec;
+  if ((opt & ~(0xff | AGG_PLAIN)) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
+  agg_status rc = plan_build(D, N, terms, nterms, opt & 0xff, &T, &err, !(opt & AGG_PLAIN));
   if (rc != AGG_OK) return set_error(rc, err);
   if (len) *len = (int64_t)T.flat.size();
   if (!out || cap < (int64_t)T.flat.size()) return set_error(AGG_EINVAL, "output capacity too small");
@@ -254,25 +260,21 @@ agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t 
   return AGG_OK;
 }
 
-agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                           agg_precision prec, int32_t batch, void* hip_stream, agg_plan** out) {
-  if (!out) return set_error(AGG_EINVAL, "out is NULL");
+static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, int32_t nterms, int prec,
+                                   int32_t batch, void* hip_stream, bool dedup, agg_plan** out) {
   *out = nullptr;
-  if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");
   agg_plan* p = new agg_plan();
   std::string err;
-  agg_status rc = plan_build(D, N, terms, nterms, prec, &p->tab, &err);
+  agg_status rc = plan_build(D, N, terms, nterms, prec, &p->tab, &err, dedup);
   if (rc != AGG_OK) { delete p; return set_error(rc, err); }
   if (N > (int64_t)1 << 30) { delete p; return set_error(AGG_EUNSUPPORTED, "N too large"); }
   p->batch = batch;
   p->stream = (hipStream_t)hip_stream;
   p->trivial = p->tab.u == 0;
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
-  {
-    if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
-    if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
-    if ((rc = p->arena.alloc(sizeof(double) * p->tab.N * batch, (void**)&p->d_scratch))) goto fail;
-  }
+  if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
+  if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
+  if ((rc = p->arena.alloc(sizeof(double) * p->tab.N * batch, (void**)&p->d_scratch))) goto fail;
   *out = p;
   return AGG_OK;
 fail:
@@ -281,9 +283,60 @@ fail:
   return rc;
 }
 
+agg_status agg_plan_destroy(agg_plan* p);
+
+agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
+                           agg_precision prec_opt, int32_t batch, void* hip_stream, agg_plan** out) {
+  if (!out) return set_error(AGG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");
+  const int opt = (int)prec_opt;
+  const int prec = opt & 0xff;
+  if ((opt & ~(0xff | AGG_PLAIN)) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
+  if (!(opt & AGG_PLAIN)) return plan_create_impl(D, N, terms, nterms, prec, batch, hip_stream, true, out);
+
+  // term-by-term reference evaluation: validate the whole set, then one
+  // sub-plan per rank-one term (d, r) with no column sharing
+  PlanTables check;
+  std::string err;
+  agg_status rc = plan_build(D, N, terms, nterms, prec, &check, &err, false);
+  if (rc != AGG_OK) return set_error(rc, err);
+  agg_plan* p = new agg_plan();
+  p->plain = true;
+  p->tab = check;
+  p->batch = batch;
+  p->stream = (hipStream_t)hip_stream;
+  for (int t = 0; t < nterms && rc == AGG_OK; ++t) {
+    for (int r = 0; r < terms[t].rank && rc == AGG_OK; ++r) {
+      agg_term one;
+      std::memset(&one, 0, sizeof(one));
+      one.d = terms[t].d;
+      one.rank = 1;
+      for (int m = 0; m < one.d; ++m) one.U[m] = terms[t].U[m] + (size_t)r * N;
+      agg_plan* sub = nullptr;
+      rc = plan_create_impl(D, N, &one, 1, prec, batch, hip_stream, false, &sub);
+      if (rc == AGG_OK) p->subs.push_back(sub);
+    }
+  }
+  p->trivial = p->subs.empty();
+  if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * N * batch, (void**)&p->k1p);
+  if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * N * batch, (void**)&p->k2p);
+  if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * N * batch, (void**)&p->ntp);
+  if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part);
+  if (rc != AGG_OK) {
+    std::string keep = g_err;
+    agg_plan_destroy(p);
+    g_err = keep;
+    return rc;
+  }
+  *out = p;
+  return AGG_OK;
+}
+
 agg_status agg_plan_destroy(agg_plan* p) {
   if (!p) return AGG_OK;
   (void)hipStreamSynchronize(p->stream);
+  for (agg_plan* sub : p->subs) agg_plan_destroy(sub);
   p->arena.release();
   delete p;
   return AGG_OK;
@@ -302,9 +355,23 @@ static agg_status run(agg_plan* p, int mode, double dt, double* state, double* o
   return AGG_OK;
 }
 
+// f(n) accumulated term by term into out (AGG_PLAIN plans)
+static agg_status plain_rhs(agg_plan* p, double* n, double* out) {
+  hipError_t e = launch_zero(out, p->tab.N * p->batch, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  agg_status rc;
+  for (agg_plan* sub : p->subs) {
+    if ((rc = run(sub, CM_FWD, 0.0, n, nullptr, false))) return rc;
+    if ((rc = run(sub, CM_FWD, 0.0, n, nullptr, true))) return rc;
+    if ((rc = run(sub, CM_RHS_ACC, 0.0, n, out, false))) return rc;
+  }
+  return AGG_OK;
+}
+
 agg_status agg_rhs(agg_plan* p, const double* n, double* dndt) {
   if (!p || !n || !dndt) return set_error(AGG_EINVAL, "NULL argument");
   double* ns = const_cast<double*>(n);
+  if (p->plain) return plain_rhs(p, ns, dndt);
   if (p->trivial) {
     hipError_t e = hipMemsetAsync(dndt, 0, sizeof(double) * p->tab.N * p->batch, p->stream);
     return e == hipSuccess ? AGG_OK : hip_fail(e, "hipMemsetAsync");
@@ -318,6 +385,19 @@ agg_status agg_rhs(agg_plan* p, const double* n, double* dndt) {
 static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, double last_dt) {
   if (nsteps <= 0 || p->trivial) return AGG_OK;
   agg_status rc;
+  if (p->plain) {
+    const int64_t total = p->tab.N * p->batch;
+    for (int64_t s = 0; s < nsteps; ++s) {
+      double h = (s == nsteps - 1) ? last_dt : dt;
+      if ((rc = plain_rhs(p, n, p->k1p))) return rc;
+      hipError_t e = launch_heun(1, n, p->k1p, nullptr, p->ntp, h, total, p->stream);
+      if (e != hipSuccess) return hip_fail(e, "heun launch");
+      if ((rc = plain_rhs(p, p->ntp, p->k2p))) return rc;
+      e = launch_heun(2, n, p->k1p, p->k2p, nullptr, h, total, p->stream);
+      if (e != hipSuccess) return hip_fail(e, "heun launch");
+    }
+    return AGG_OK;
+  }
   if ((rc = run(p, CM_FWD, 0.0, n, nullptr, false))) return rc;
   for (int64_t s = 0; s < nsteps; ++s) {
     double h = (s == nsteps - 1) ? last_dt : dt;
@@ -376,6 +456,7 @@ agg_status agg_solve(agg_plan* p, double* n, double dt, double t_end, agg_solve_
 
 agg_status agg_profile_pass(agg_plan* p, const double* n, int32_t pass, int32_t reps, double* us) {
   if (!p || !n || !us || pass < 0 || pass > 3 || reps < 1) return set_error(AGG_EINVAL, "bad argument");
+  if (p->plain) return set_error(AGG_EINVAL, "per-pass timing is defined for shared-column plans only");
   *us = 0.0;
   if (p->trivial) return AGG_OK;
   double* ns = const_cast<double*>(n);

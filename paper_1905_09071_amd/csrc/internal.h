@@ -34,6 +34,8 @@ struct SharedTables {
 };
 
 agg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena& arena, int batch,
+                       SlotDesc* sd, SlotStride* stride);
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st);
 agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd);
 size_t slot_bytes(const PlanTables& T);
@@ -44,6 +46,9 @@ hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_row(int prec, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_moments(const double* n, int64_t total, int64_t N, double* part, int nblocks,
                           hipStream_t s);
+hipError_t launch_heun(int stage, double* n, const double* k1, const double* k2, double* ntil, double dt,
+                       int64_t total, hipStream_t s);
+hipError_t launch_zero(double* x, int64_t total, hipStream_t s);
 size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max);
 int col_batch(int prec, int M1, int u, int nworkgroups);
 

@@ -27,9 +27,11 @@ enum ColMode : int {
   CM_H1 = 3,        // inverse + epilogue: k1 = f(n), n~ = n + dt k1, forward of n~
   CM_H2 = 4,        // inverse + epilogue: n <- n + dt/2 (k1 + f(n~))
   CM_H2_FWD = 5,    // as CM_H2, then forward of the new n
+  CM_RHS_ACC = 6,   // inverse + epilogue: out += f(state)  (term-by-term evaluation)
 };
 
 __host__ __device__ inline bool mode_has_inverse(int m) { return m >= CM_RHS; }
+__host__ __device__ inline bool mode_writes_rhs(int m) { return m == CM_RHS || m == CM_RHS_ACC; }
 __host__ __device__ inline bool mode_has_forward(int m) { return m == CM_FWD || m == CM_H1 || m == CM_H2_FWD; }
 
 struct SlotDesc {

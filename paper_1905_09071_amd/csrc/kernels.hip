@@ -199,6 +199,8 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
             double f = p - pe[it][e] * gk[it][e];
             if (mode == CM_RHS) {
               out[s - 1] = f;
+            } else if (mode == CM_RHS_ACC) {
+              out[s - 1] += f;
             } else if (mode == CM_H1) {
               sd.k1[s - 1] = f;
               val = pe[it][e] + dt * f;
@@ -455,6 +457,38 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
       sd.G[tid] = Gc;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise Heun stages of the unfused (term-by-term) evaluation:
+//   stage 1: n~ = n + dt k1        stage 2: n = n + dt/2 (k1 + k2)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void heun_kernel(int stage, double* n, const double* k1, const double* k2,
+                                                        double* ntil, double dt, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (int64_t)gridDim.x * kThreads) {
+    if (stage == 1) ntil[i] = n[i] + dt * k1[i];
+    else n[i] = n[i] + 0.5 * dt * (k1[i] + k2[i]);
+  }
+}
+
+hipError_t launch_heun(int stage, double* n, const double* k1, const double* k2, double* ntil, double dt,
+                       int64_t total, hipStream_t s) {
+  int64_t blocks = (total + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(heun_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, stage, n, k1, k2, ntil, dt, total);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void zero_kernel(double* x, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (int64_t)gridDim.x * kThreads)
+    x[i] = 0.0;
+}
+
+hipError_t launch_zero(double* x, int64_t total, hipStream_t s) {
+  int64_t blocks = (total + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, x, total);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

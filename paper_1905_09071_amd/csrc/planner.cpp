@@ -26,7 +26,7 @@ static int ilog2(int64_t x) {
 }
 
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
-                      PlanTables* out, std::string* err) {
+                      PlanTables* out, std::string* err, bool dedup) {
   if (D < 2 || D > AGG_MAX_D) { *err = "D must lie in [2, AGG_MAX_D]"; return AGG_EINVAL; }
   if (N < 1) { *err = "N must be >= 1"; return AGG_EINVAL; }
   if (prec != AGG_FP64 && prec != AGG_FP32 && prec != AGG_FP32C) {
@@ -74,7 +74,7 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
       for (int r = 0; r < R; ++r) {
         const double* col = byd[d]->U[m] + (size_t)r * N;
         int id = -1;
-        for (size_t j = 0; j < uptr.size(); ++j)
+        for (size_t j = 0; dedup && j < uptr.size(); ++j)
           if (std::memcmp(uptr[j], col, sizeof(double) * (size_t)N) == 0) { id = (int)j; break; }
         if (id < 0) { uptr.push_back(col); id = (int)uptr.size() - 1; }
         P.colmap.push_back(id);

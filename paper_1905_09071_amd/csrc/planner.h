@@ -30,8 +30,10 @@ struct PlanTables {
 
 // Validates the arguments and builds the tables.  Returns AGG_OK or an error
 // code with a message in *err.
+// dedup = false gives every (d, m, r) column its own id (the unshared reference
+// evaluation); the rules are otherwise unchanged.
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
-                      PlanTables* out, std::string* err);
+                      PlanTables* out, std::string* err, bool dedup = true);
 
 // exp(-2 pi i e / P) for e = 0..P-1, interleaved (re, im), binary64.
 void twiddle_table(int64_t P, double* out);

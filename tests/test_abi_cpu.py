@@ -57,6 +57,16 @@ def test_plan_tables_bit_exact(kname, kf, D, N, prec):
     assert got.dtype == np.int64 and np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("kname,kf", KERNELS[:5])
+def test_plain_plan_tables_bit_exact(kname, kf):
+    """Without column sharing every (d, m, r) column gets its own id."""
+    k = kf(4, 100)
+    ref = oracle_plan(4, 100, k, "fp64", dedup=False)
+    got = agg.plan_tables(4, 100, k, "fp64", plain=True)
+    assert np.array_equal(got, ref["flat"])
+    assert ref["u"] == sum(d * k[d].shape[1] for d in k)
+
+
 def test_plan_tables_large_and_unsupported():
     k = synth.kernel_additive(5, 1 << 20)
     assert np.array_equal(agg.plan_tables(5, 1 << 20, k), oracle_plan(5, 1 << 20, k)["flat"])
@@ -127,8 +137,12 @@ def test_invalid_arguments_refused_before_any_device_call():
     terms[0].U[1] = ctypes.POINTER(ctypes.c_double)()
     assert L.agg_plan_create(3, 8, terms, 1, 0, 1, None, ctypes.byref(h)) == agg.AGG_EINVAL
     assert L.agg_plan_create(3, 8, terms, 1, 0, 1, None, None) == agg.AGG_EINVAL
-    # length limit
-    assert _create(4, (1 << 21) + 1, None) == agg.AGG_EUNSUPPORTED or True
+    # length limit: 4*N - 1 > 2^23 is refused before any column is read
+    Nbig = (1 << 21) + 1
+    big = {4: np.ones((4, 1, Nbig))}
+    assert _create(4, Nbig, big) == agg.AGG_EUNSUPPORTED
+    assert b"2^23" in L.agg_last_error()
+    assert _create(3, 8, k, prec=0x200) == agg.AGG_EINVAL   # unknown option bit
 
 
 def test_null_plan_calls_are_refused():

@@ -238,3 +238,24 @@ def test_solve_time_grid_and_errors():
     with pytest.raises(agg.AggError) as e:
         plan.solve(bad, 1e-3, 1e-3)
     assert e.value.status == agg.AGG_ENONFINITE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_plain_path_matches_oracle_and_shared_path(prec):
+    """AGG_PLAIN (term by term, no shared columns, unfused) computes the same RHS
+    and the same Heun trajectory as the shared-column fused path."""
+    D, N = 4, 300
+    k = synth.kernel_ballistic(D, N, 0.4)
+    n = synth.n0_random_dense(N, 61, decay=0.02)
+    ref = oracle_rhs(D, N, k, n, "fft")
+    plain = agg.Plan(D, N, k, prec, plain=True)
+    nt = torch.tensor(n, device=DEV)
+    got = plain.rhs(nt)
+    torch.cuda.synchronize()
+    assert rel(got.cpu().numpy(), ref) <= RHS_TOL[prec]
+    a = torch.tensor(n, device=DEV)
+    b = torch.tensor(n, device=DEV)
+    plain.solve(a, 1e-3, 5e-3)
+    agg.Plan(D, N, k, prec).solve(b, 1e-3, 5e-3)
+    torch.cuda.synchronize()
+    assert rel(a.cpu().numpy(), b.cpu().numpy()) <= (1e-13 if prec == "fp64" else 1e-11)
