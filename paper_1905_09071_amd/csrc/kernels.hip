@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
   constexpr int CAP = GMAX * M1;
   constexpr int IPT = (CAP + NT - 1) / NT;
   constexpr int NWAVE = NT / 64;
-  constexpr int UP = kColPrefetch;
+  constexpr int UP = IPT <= 2 ? kColPrefetch : 2;   // register budget at the largest M1
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* tw = (cplx<T>*)smem;
   cplx<T>* buf = tw + M1;
@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
       if (lane == 0) red[wave][c - cb] = dsum;
     }
     lds_barrier();
-    fft_batch<T, M1, -1, GMAX * kColBatch, STR, NT>(buf, nc * g, tw);
+    // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
+    fft_batch<T, M1, -1, GMAX * (M1 >= 2048 ? 2 : kColBatch), STR, NT>(buf, nc * g, tw);
     for (int q = 0; q < nc; ++q) {
 #pragma unroll
       for (int it = 0; it < IPT; ++it) {
