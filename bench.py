@@ -117,6 +117,12 @@ def main():
     ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64", "fp32"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU sample budget (0 = skip)")
     ap.add_argument("--serving", type=int, default=64, help="requests in the serving sample (0 = skip)")
+    ap.add_argument("--batch", type=int, default=64, help="states of the batched C3 line (0 = skip)")
+    ap.add_argument("--c5", type=int, default=1, help="run the D=5 N=2^20 batch-64 line (0 = skip)")
+    ap.add_argument("--quick", action="store_true",
+                    help="profiling aid: time only the primary precision, no pass timing, no other lines")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="profiling aid: also copy a float64 tensor of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -136,19 +142,39 @@ def main():
     M = L // 2
     log(f"[bench] C3 D={D} N={N} L={L} M1={M1} M2={M2} g={g} u={u} steps={args.steps} warmup={args.warmup}")
 
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * 131072, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe} MiB copied")
+        del src, dst
+
     results = {}
     order = [args.prec] + [p for p in ("fp64", "fp32", "fp32c") if p != args.prec]
+    if args.quick:
+        order = [args.prec]
     for prec in order:
         plan = agg.Plan(D, N, c["kernel"], prec)
         n = torch.tensor(c["n0"], dtype=torch.float64, device="cuda:0")
         t_gpu, t_wall = time_steps(plan, n, dt, args.steps, args.warmup, torch)
         rate = 2 * args.steps / t_gpu
+        if args.quick:
+            results[prec] = dict(seconds=t_gpu, wall=t_wall, rhs_per_s=rate, passes_us={w: 1.0 for w in range(4)})
+            log(f"[bench] {prec}: {args.steps} steps in {t_gpu*1e3:.2f} ms -> {rate:.1f} RHS/s (quick)")
+            plan.close()
+            del n
+            continue
         passes = {w: plan.profile_pass(n, w, reps=200) for w in (0, 1, 2, 3)}
         results[prec] = dict(seconds=t_gpu, wall=t_wall, rhs_per_s=rate, passes_us=passes)
         log(f"[bench] {prec}: {args.steps} steps in {t_gpu*1e3:.2f} ms (wall {t_wall*1e3:.2f}) -> "
             f"{rate:.1f} RHS/s; pass us: " + ", ".join(f"{w}:{v:.2f}" for w, v in passes.items()))
         plan.close()
         del n
+
+    if args.quick:
+        print(json.dumps({"quick": True, "prec": args.prec, "rhs_per_s": round(results[args.prec]["rhs_per_s"], 2)}))
+        return
 
     # the plain fp64 reference evaluation (term by term, unshared, unfused)
     plan = agg.Plan(D, N, c["kernel"], "fp64", plain=True)
@@ -159,6 +185,35 @@ def main():
     log(f"[bench] plain fp64: {psteps} steps in {t_plain*1e3:.2f} ms -> {plain_rate:.1f} RHS/s")
     plan.close()
     del n
+
+    # batched throughput: B states sharing the kernel (C3 shape) and the D=5,
+    # N=2^20 batch of 64 states (transform length 2^23)
+    batched = {}
+    if args.batch > 0:
+        for prec in ("fp64", "fp32c"):
+            plan = agg.Plan(D, N, c["kernel"], prec, batch=args.batch)
+            n = torch.tensor(np.tile(c["n0"], args.batch), dtype=torch.float64, device="cuda:0")
+            bsteps = 20
+            t_b, _ = time_steps(plan, n, dt, bsteps, 2, torch)
+            batched[prec] = round(2 * bsteps * args.batch / t_b, 1)
+            log(f"[bench] C3 batch {args.batch} {prec}: {2 * bsteps * args.batch / t_b:.1f} RHS/s")
+            plan.close()
+            del n
+            torch.cuda.empty_cache()
+    c5 = {}
+    if args.c5:
+        cc = synth.config("C5a")
+        B5 = cc["n0"].shape[0]
+        for prec in ("fp64", "fp32c"):
+            plan = agg.Plan(cc["D"], cc["N"], cc["kernel"], prec, batch=B5)
+            n = torch.tensor(cc["n0"].reshape(-1), dtype=torch.float64, device="cuda:0")
+            s5 = 10
+            t5, _ = time_steps(plan, n, cc["dt"], s5, 1, torch)
+            c5[prec] = round(2 * s5 * B5 / t5, 2)
+            log(f"[bench] D=5 N=2^20 batch {B5} {prec}: {s5} steps in {t5*1e3:.1f} ms -> {c5[prec]} RHS/s")
+            plan.close()
+            del n
+            torch.cuda.empty_cache()
 
     prim = results[args.prec]
     cs = PREC_BYTES[args.prec]
@@ -204,6 +259,8 @@ def main():
         "rhs_per_s": {p: round(r["rhs_per_s"], 2) for p, r in results.items()},
         "ratio_fp32c_vs_fp64": round(results["fp32c"]["rhs_per_s"] / results["fp64"]["rhs_per_s"], 4),
         "plain_fp64_rhs_per_s": round(plain_rate, 2),
+        "batched_rhs_per_s": {"batch": args.batch, **batched} if batched else None,
+        "d5_n2e20_batch64_rhs_per_s": c5 or None,
         "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,
