@@ -207,6 +207,7 @@ LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc
   a.M1 = T.M1; a.M2 = T.M2; a.g = T.g; a.b = T.b; a.L = T.L;
   a.umax = std::max(T.u, 1);
   a.ub = col_batch(T.prec, T.M1, T.u, nslots * (T.M2 / T.g));
+  a.lean = nslots * (T.M2 / T.g) >= kLeanWorkgroups ? 1 : 0;
   a.lgg = 0;
   while ((1 << a.lgg) < T.g) ++a.lgg;
   a.tab_max = st.ntab;

@@ -206,6 +206,7 @@ void Engine::tick() {
         }
     a.umax = umax;
     a.ub = col_batch(first->tab.prec, first->tab.M1, umax, cnt * (first->tab.M2 / first->tab.g));
+    a.lean = cnt * (first->tab.M2 / first->tab.g) >= kLeanWorkgroups ? 1 : 0;
     a.tab_max = tpm;
     a.coef_max = tidm;
     e = launch_row(first->tab.prec, a, stream);

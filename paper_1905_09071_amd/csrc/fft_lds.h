@@ -127,13 +127,13 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int nfft, const cplx<T>*
   lds_barrier();
 }
 
-template <class T, int P, int NS, int DIR, int NB, int STR, int NT>
+template <class T, int P, int NS, int DIR, int NB, int STR, int NT, int RMAX>
 __device__ __forceinline__ void fft_stages(cplx<T>* buf, int nfft, const cplx<T>* __restrict__ tw) {
   if constexpr (NS < P) {
     constexpr int REM = P / NS;
-    constexpr int R = REM >= 8 ? 8 : REM;
+    constexpr int R = REM >= RMAX ? RMAX : REM;
     fft_stage<T, P, R, NS, DIR, NB, STR, NT>(buf, nfft, tw);
-    fft_stages<T, P, NS * R, DIR, NB, STR, NT>(buf, nfft, tw);
+    fft_stages<T, P, NS * R, DIR, NB, STR, NT, RMAX>(buf, nfft, tw);
   }
 }
 
@@ -142,11 +142,14 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, int nfft, const cplx<T>
 // thread of the block must call this (it synchronises internally, on LDS only:
 // the caller must have made its LDS input visible with lds_barrier() or
 // __syncthreads() first).
-template <class T, int P, int DIR, int NB, int STR, int NT = kThreads>
+// RMAX: largest radix per stage.  Radix 8 needs the fewest LDS passes (best
+// when many workgroups share a CU); radix 4 gives shorter per-thread chains and
+// more parallel butterflies (best when one workgroup per CU is latency-bound).
+template <class T, int P, int DIR, int NB, int STR, int NT = kThreads, int RMAX = 8>
 __device__ __forceinline__ void fft_batch(cplx<T>* buf, int count, const cplx<T>* __restrict__ tw) {
   for (int c0 = 0; c0 < count; c0 += NB) {
     int nf = count - c0 < NB ? count - c0 : NB;
-    fft_stages<T, P, 1, DIR, NB, STR, NT>(buf + c0 * STR, nf, tw);
+    fft_stages<T, P, 1, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, nf, tw);
   }
 }
 

@@ -81,11 +81,13 @@ struct LaunchArgs {
   int ub;                 // forward columns transformed together in the column pass
   int tab_max;            // largest term-table int blob among the slots
   int coef_max;           // largest coefficient blob (Tp + Tq) among the slots
+  int lean;               // column pass variant for launches that fill the GPU
 };
 
 constexpr int kColBatch = 4;             // upper bound of LaunchArgs::ub
 constexpr int kColThreads = 512;         // threads of a column-pass workgroup
 constexpr int kColPrefetch = 4;          // factor columns held in registers by the column pass
 constexpr int kColLdsBudget = 120 * 1024; // LDS the column pass may use
+constexpr int kLeanWorkgroups = 512;     // column-pass workgroups from which a launch counts as saturating
 
 }  // namespace agg

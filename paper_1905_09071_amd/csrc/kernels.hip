@@ -20,12 +20,53 @@
 
 namespace agg {
 
+// Largest radix of the in-LDS transform stages: radix 4 for float-float (its
+// long arithmetic chains favour more, shorter butterflies), radix 8 otherwise
+// (fewer LDS passes).  Measured on the D=4, N=65536 workload.
+template <class T> struct StageRadix { static constexpr int value = 8; };
+template <> struct StageRadix<ff> { static constexpr int value = 4; };
+
+// Loads and stores of device memory through global-address-space pointers.
+// Pointers taken from descriptors and launch structs would otherwise compile
+// to flat (generic) accesses, which also count against the LDS wait counter:
+// every LDS barrier would then wait for all prefetched global loads.
+// Class types (complex values, descriptors) move as 8-byte words.
+typedef unsigned int gword __attribute__((ext_vector_type(2)));
+template <class T> __device__ __forceinline__ T ldg(const T* p) {
+  if constexpr (__is_class(T)) {
+    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 4, "8-byte words");
+    constexpr int W = sizeof(T) / 8;
+    gword w[W];
+    const __attribute__((address_space(1))) gword* q = (const __attribute__((address_space(1))) gword*)p;
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = q[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+  } else {
+    return *(const __attribute__((address_space(1))) T*)p;
+  }
+}
+template <class T> __device__ __forceinline__ void stg(T* p, T v) {
+  if constexpr (__is_class(T)) {
+    static_assert(sizeof(T) % 8 == 0, "8-byte words");
+    constexpr int W = sizeof(T) / 8;
+    gword w[W];
+    __builtin_memcpy(w, &v, sizeof(T));
+    __attribute__((address_space(1))) gword* q = (__attribute__((address_space(1))) gword*)p;
+#pragma unroll
+    for (int i = 0; i < W; ++i) q[i] = w[i];
+  } else {
+    *(__attribute__((address_space(1))) T*)p = v;
+  }
+}
+
 template <class T>
 __device__ __forceinline__ cplx<T> twL(const LaunchArgs& a, int64_t e) {
   const cplx<T>* lo = (const cplx<T>*)a.twLlo;
   const cplx<T>* hi = (const cplx<T>*)a.twLhi;
   int64_t mask = (int64_t(1) << a.b) - 1;
-  return cmul(hi[e >> a.b], lo[e & mask]);
+  return cmul(ldg(hi + (e >> a.b)), ldg(lo + (e & mask)));
 }
 
 // Sum over the 64 lanes of a wavefront (xor butterfly: every lane ends with the
@@ -39,7 +80,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Descriptor of one slot: from device memory, or built from the launch's base
 // descriptor and strides (no dependent load before the first data request).
 __device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
-  if (a.slots) return a.slots[slot];
+  if (a.slots) return ldg(a.slots + slot);
   SlotDesc sd = a.base;
   sd.k1 = (double*)((char*)sd.k1 + slot * a.stride.k1);
   sd.ntil = (double*)((char*)sd.ntil + slot * a.stride.ntil);
@@ -57,11 +98,11 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nb) {
   return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
-template <class T, int NUM>
+template <class T, int NUM, int NT>
 __device__ __forceinline__ void load_table(cplx<T>* dst, const void* src) {
   const cplx<T>* s = (const cplx<T>*)src;
 #pragma unroll
-  for (int i = threadIdx.x; i < NUM; i += kThreads) dst[i] = s[i];
+  for (int i = threadIdx.x; i < NUM; i += NT) dst[i] = ldg(s + i);
 }
 
 // ---------------------------------------------------------------------------
@@ -72,15 +113,19 @@ __device__ __forceinline__ void load_table(cplx<T>* dst, const void* src) {
 // four-step twiddles) is requested in one round at the start, so a launch
 // costs about three memory round trips: descriptor, data, stores.
 // ---------------------------------------------------------------------------
-template <class T, int M1>
-__global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
+// LEAN (used when a launch already fills the GPU): no factor columns or Heun
+// vectors held in registers, and a register budget that lets two workgroups
+// share a CU, so one workgroup's memory wait overlaps another's arithmetic.
+template <class T, int M1, bool LEAN>
+__global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchArgs a) {
   constexpr int NT = kColThreads;
   constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
   constexpr int STR = lds_len(M1);
   constexpr int CAP = GMAX * M1;
   constexpr int IPT = (CAP + NT - 1) / NT;
   constexpr int NWAVE = NT / 64;
-  constexpr int UP = IPT <= 2 ? kColPrefetch : 2;   // register budget at the largest M1
+  constexpr int UP = LEAN ? 0 : (IPT <= 2 ? kColPrefetch : 2);   // register budget at the largest M1
+  constexpr int UPA = UP > 0 ? UP : 1;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* tw = (cplx<T>*)smem;
   cplx<T>* buf = tw + M1;
@@ -107,10 +152,27 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
   double* state = a.ext_state ? a.ext_state + (size_t)slot * N : sd.n_state;
   const double* ev = stage2 ? sd.ntil : state;   // state at which f is taken
 
-  // ---- one round of global requests ----
-  load_table<T, M1>(tw, a.twP1);
+  // ---- one round of global requests, issued in the order they are needed
+  // (completions are counted in issue order) ----
+  constexpr int TPT = (M1 + NT - 1) / NT;
+  cplx<T> vreg[IPT], twreg[TPT];
+  const cplx<T>* V = (const cplx<T>*)sd.V;
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    int idx = tid + it * NT;
+    int k1 = idx >> lgg, jl = idx & (g - 1);
+    vreg[it] = (inv && idx < nitems) ? ldg(V + ((int64_t)k1 * M2 + j2_0 + jl)) : czero<T>();
+  }
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    int e = tid + i * NT;
+    twreg[i] = e < M1 ? ldg((const cplx<T>*)a.twP1 + e) : czero<T>();
+  }
+  double Gv[UPA];
+#pragma unroll
+  for (int q = 0; q < UPA; ++q) Gv[q] = (inv && q < u) ? ldg(sd.G + q) : 0.0;
   int64_t pos[IPT];          // size 2j of each item (2j+1 is the odd partner)
-  double pe[IPT][2], pn[IPT][2], pk[IPT][2], uc[UP][IPT][2];
+  double pe[IPT][2], pn[IPT][2], pk[IPT][2], uc[UPA][IPT][2];
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     int idx = tid + it * NT;
@@ -120,37 +182,41 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
     for (int e = 0; e < 2; ++e) {
       int64_t s = pos[it] + e;
       bool ok = s >= 1 && s <= N;
-      pe[it][e] = ok ? ev[s - 1] : 0.0;
-      pn[it][e] = (ok && stage2) ? state[s - 1] : 0.0;
-      pk[it][e] = (ok && stage2) ? sd.k1[s - 1] : 0.0;
+      pe[it][e] = ok ? ldg(ev + (s - 1)) : 0.0;
+      pn[it][e] = (!LEAN && ok && stage2) ? ldg(state + (s - 1)) : 0.0;
+      pk[it][e] = (!LEAN && ok && stage2) ? ldg(sd.k1 + (s - 1)) : 0.0;
 #pragma unroll
-      for (int q = 0; q < UP; ++q) uc[q][it][e] = (ok && q < u) ? sd.cols[(size_t)q * N + (s - 1)] : 0.0;
+      for (int q = 0; q < UP; ++q) uc[q][it][e] = (ok && q < u) ? ldg(sd.cols + ((size_t)q * N + (s - 1))) : 0.0;
     }
   }
-  cplx<T> wst[IPT];          // four-step twiddles w_M^(j2 k1), shared by all columns
+  // four-step twiddles w_M^(j2 k1) (two table halves; multiplied when used)
+  cplx<T> wsh[IPT], wsl[IPT];
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     int idx = tid + it * NT;
     int k1 = idx >> lgg, jl = idx & (g - 1);
     int64_t e = (2 * (int64_t)(j2_0 + jl) * k1) & (a.L - 1);
-    wst[it] = (fwd && idx < nitems) ? twL<T>(a, e) : czero<T>();
+    bool ok = fwd && idx < nitems;
+    wsh[it] = ok ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
+    wsl[it] = ok ? ldg((const cplx<T>*)a.twLlo + (e & ((int64_t(1) << a.b) - 1))) : czero<T>();
   }
-  if (inv) {
-    const cplx<T>* V = (const cplx<T>*)sd.V;
+  // the spectrum block and the twiddle table go to LDS (waits only for them)
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-      int idx = tid + it * NT;
-      if (idx < nitems) {
-        int k1 = idx >> lgg, jl = idx & (g - 1);
-        buf[jl * STR + lds_pad(k1)] = V[(int64_t)k1 * M2 + j2_0 + jl];
-      }
-    }
+  for (int it = 0; it < IPT; ++it) {
+    int idx = tid + it * NT;
+    int k1 = idx >> lgg, jl = idx & (g - 1);
+    if (inv && idx < nitems) buf[jl * STR + lds_pad(k1)] = vreg[it];
+  }
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    int e = tid + i * NT;
+    if (e < M1) tw[e] = twreg[i];
   }
 
   double s0[IPT], s1[IPT];   // state the forward pass weights, at sizes 2j, 2j+1
   if (inv) {
     lds_barrier();
-    fft_batch<T, M1, +1, GMAX, STR, NT>(buf, g, tw);
+    fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, g, tw);
 
     // loss weight g_k = sum_c U_c(k) G_c
     double gk[IPT][2];
@@ -159,7 +225,7 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
 #pragma unroll
     for (int q = 0; q < UP; ++q) {
       if (q < u) {
-        const double Gc = sd.G[q];
+        const double Gc = Gv[q];
 #pragma unroll
         for (int it = 0; it < IPT; ++it) {
           gk[it][0] += uc[q][it][0] * Gc;
@@ -168,14 +234,14 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
       }
     }
     for (int c = UP; c < u; ++c) {
-      const double Gc = sd.G[c];
+      const double Gc = ldg(sd.G + c);
       const double* col = sd.cols + (size_t)c * N;
 #pragma unroll
       for (int it = 0; it < IPT; ++it)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           int64_t s = pos[it] + e;
-          if (s >= 1 && s <= N) gk[it][e] += col[s - 1] * Gc;
+          if (s >= 1 && s <= N) gk[it][e] += ldg(col + (s - 1)) * Gc;
         }
     }
 
@@ -198,16 +264,18 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
             double p = s >= 2 ? y[e] * invL : 0.0;
             double f = p - pe[it][e] * gk[it][e];
             if (mode == CM_RHS) {
-              out[s - 1] = f;
+              stg(out + (s - 1), f);
             } else if (mode == CM_RHS_ACC) {
-              out[s - 1] += f;
+              stg(out + (s - 1), ldg(out + (s - 1)) + f);
             } else if (mode == CM_H1) {
-              sd.k1[s - 1] = f;
+              stg(sd.k1 + (s - 1), f);
               val = pe[it][e] + dt * f;
-              sd.ntil[s - 1] = val;
+              stg(sd.ntil + (s - 1), val);
             } else {
-              val = pn[it][e] + 0.5 * dt * (pk[it][e] + f);
-              state[s - 1] = val;
+              const double nb = LEAN ? ldg(state + (s - 1)) : pn[it][e];
+              const double kb = LEAN ? ldg(sd.k1 + (s - 1)) : pk[it][e];
+              val = nb + 0.5 * dt * (kb + f);
+              stg(state + (s - 1), val);
             }
           }
           if (e == 0) s0[it] = val; else s1[it] = val;
@@ -224,6 +292,9 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
     }
   }
 
+  cplx<T> wst[IPT];
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) wst[it] = cmul(wsh[it], wsl[it]);
   cplx<T>* Z1 = (cplx<T>*)sd.Z1;
   for (int cb = 0; cb < u; cb += a.ub) {
     const int nc = u - cb < a.ub ? u - cb : a.ub;
@@ -256,8 +327,8 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
         if (idx < nitems) {
           int j1 = idx >> lgg, jl = idx & (g - 1);
           int64_t s = pos[it];
-          double x0 = (s >= 1 && s <= N) ? col[s - 1] * s0[it] : 0.0;
-          double x1 = (s + 1 <= N) ? col[s] * s1[it] : 0.0;
+          double x0 = (s >= 1 && s <= N) ? ldg(col + (s - 1)) * s0[it] : 0.0;
+          double x1 = (s + 1 <= N) ? ldg(col + s) * s1[it] : 0.0;
           buf[((c - cb) * g + jl) * STR + lds_pad(j1)] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
           dsum += x0 + x1;
         }
@@ -267,15 +338,15 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
     }
     lds_barrier();
     // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
-    fft_batch<T, M1, -1, GMAX * (M1 >= 2048 ? 2 : kColBatch), STR, NT>(buf, nc * g, tw);
+    fft_batch<T, M1, -1, GMAX * (M1 >= 2048 ? 2 : kColBatch), STR, NT, StageRadix<T>::value>(buf, nc * g, tw);
     for (int q = 0; q < nc; ++q) {
 #pragma unroll
       for (int it = 0; it < IPT; ++it) {
         int idx = tid + it * NT;
         if (idx < nitems) {
           int k1 = idx >> lgg, jl = idx & (g - 1);
-          Z1[(size_t)(cb + q) * M + (int64_t)k1 * M2 + j2_0 + jl] =
-              cmul(buf[(q * g + jl) * STR + lds_pad(k1)], wst[it]);
+          stg(Z1 + ((size_t)(cb + q) * M + (int64_t)k1 * M2 + j2_0 + jl),
+              cmul(buf[(q * g + jl) * STR + lds_pad(k1)], wst[it]));
         }
       }
     }
@@ -283,7 +354,7 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
       double t = 0.0;
 #pragma unroll
       for (int wv = 0; wv < NWAVE; ++wv) t += red[wv][tid];
-      sd.dots[(size_t)(cb + tid) * ngroups + grp] = t;
+      stg(sd.dots + ((size_t)(cb + tid) * ngroups + grp), t);
     }
     lds_barrier();
   }
@@ -295,7 +366,7 @@ __global__ __launch_bounds__(kColThreads) void col_kernel(LaunchArgs a) {
 // gain-term tables, u*nrows rows, u Nyquist values.
 // ---------------------------------------------------------------------------
 template <class T, int M2>
-__global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(kThreads, M2 <= 512 ? 5 : 1) void row_kernel(LaunchArgs a) {
   constexpr bool TW_LDS = M2 <= 512;
   constexpr int NB = (2048 / M2) > 0 ? 2048 / M2 : 1;
   constexpr int STR = lds_len(M2);
@@ -330,44 +401,49 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
   const int rows[2] = {k1, M1 - k1};
   const int Tp = sd.Tp;
 
-  // everything this work item reads from HBM is requested up front
-  if (TW_LDS) load_table<T, M2>(twl, a.twP2);
-  for (int i = tid; i < sd.ntab; i += kThreads) tab[i] = sd.tab[i];
-  for (int i = tid; i < Tp + sd.Tq; i += kThreads) coef[i] = sd.coef[i];
+  // everything this work item reads from HBM is requested up front, in the
+  // order it is needed (completions are counted in issue order)
   const cplx<T>* Z1 = (const cplx<T>*)sd.Z1;
   const int nload = u * nrows * M2;
 #pragma unroll 8
   for (int idx = tid; idx < nload; idx += kThreads) {
     int cr = idx / M2, k2 = idx - cr * M2;
     int c = cr / nrows, rr = cr - c * nrows;
-    X[cr * STR + lds_pad(k2)] = Z1[(size_t)c * M + (int64_t)rows[rr] * M2 + k2];
+    X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)c * M + (int64_t)rows[rr] * M2 + k2));
   }
+  if (TW_LDS) load_table<T, M2, kThreads>(twl, a.twP2);
   const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
-  cplx<T> wku[UPT];   // w_L^k of this thread's combine units
+  const int64_t lmask = (int64_t(1) << a.b) - 1;
+  cplx<T> wkh[UPT], wkl[UPT];   // w_L^k of this thread's combine units (two table halves)
 #pragma unroll
   for (int i = 0; i < UPT; ++i) {
     int unit = tid + i * kThreads;
-    wku[i] = unit < nunits ? twL<T>(a, k1 + (int64_t)M1 * unit) : czero<T>();
+    int64_t e = k1 + (int64_t)M1 * unit;
+    wkh[i] = unit < nunits ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
+    wkl[i] = unit < nunits ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
   }
-  cplx<T> wvo[VPT];   // w_M^(-j2 row) of this thread's outputs (conjugated at use)
+  cplx<T> wvh[VPT], wvl[VPT];   // w_M^(j2 row) of this thread's outputs (conjugated at use)
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
     int idx = tid + i * kThreads;
     int rr = idx / M2, j2 = idx - rr * M2;
     int64_t e = (2 * (int64_t)j2 * rows[rr < 2 ? rr : 0]) & (a.L - 1);
-    wvo[i] = idx < nrows * M2 ? twL<T>(a, e) : czero<T>();
+    wvh[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
+    wvl[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
   }
+  for (int i = tid; i < sd.ntab; i += kThreads) tab[i] = ldg(sd.tab + i);
+  for (int i = tid; i < Tp + sd.Tq; i += kThreads) coef[i] = ldg(sd.coef + i);
   if (k1 == 0) {   // partial dots of the column pass -> per-wave sums
     const int ngroups = M2 / a.g;
     for (int c = 0; c < u; ++c) {
       double sacc = 0.0;
-      for (int q = tid; q < ngroups; q += kThreads) sacc += sd.dots[(size_t)c * ngroups + q];
+      for (int q = tid; q < ngroups; q += kThreads) sacc += ldg(sd.dots + ((size_t)c * ngroups + q));
       sacc = wave_sum(sacc);
       if (lane == 0) red[wave * a.umax + c] = sacc;
     }
   }
   lds_barrier();
-  fft_batch<T, M2, -1, NB, STR>(X, u * nrows, tw);
+  fft_batch<T, M2, -1, NB, STR, kThreads, StageRadix<T>::value>(X, u * nrows, tw);
 
   // bins k = k1 + M1*iA and M - k, spectra of the real inputs, their weighted
   // products, and the even/odd packing of the real inverse
@@ -384,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
     else { iB = M2 - 1 - iA; rB = 1; }
     const bool zero_bin = (k1 == 0 && iA == 0);
     const bool self = (rB == 0 && iB == iA);
-    const cplx<T> wk = wku[i];
+    const cplx<T> wk = cmul(wkh[i], wkl[i]);
     for (int c = 0; c < u; ++c) {
       cplx<T>* pA = &X[(c * nrows) * STR + lds_pad(iA)];
       cplx<T>* pB = &X[(c * nrows + rB) * STR + lds_pad(iB)];
@@ -423,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
     }
   }
   lds_barrier();
-  fft_batch<T, M2, +1, NB, STR>(X, nrows, tw);
+  fft_batch<T, M2, +1, NB, STR, kThreads, StageRadix<T>::value>(X, nrows, tw);
 
   cplx<T>* V = (cplx<T>*)sd.V;
 #pragma unroll
@@ -431,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
     int idx = tid + i * kThreads;
     if (idx < nrows * M2) {
       int rr = idx / M2, j2 = idx - rr * M2;
-      V[(int64_t)rows[rr] * M2 + j2] = cmulc(X[rr * STR + lds_pad(j2)], wvo[i]);
+      stg(V + ((int64_t)rows[rr] * M2 + j2), cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i])));
     }
   }
 
@@ -455,7 +531,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(LaunchArgs a) {
         for (int o = qoff[t]; o < qoff[t + 1]; ++o) pr *= sdot[qids[o]];
         Gc += pr;
       }
-      sd.G[tid] = Gc;
+      stg(sd.G + tid, Gc);
     }
   }
 }
@@ -523,20 +599,26 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(const double* n, int6
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-template <class T, int M1>
-static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
+template <class T, int M1, bool LEAN>
+static hipError_t launch_col_v(const LaunchArgs& a, hipStream_t s, size_t smem, dim3 grid) {
   static bool attr_done = false;   // raise the dynamic LDS cap once per instantiation
   if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void*)col_kernel<T, M1>,
+    hipError_t e = hipFuncSetAttribute((const void*)col_kernel<T, M1, LEAN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kColLdsBudget + 16384);
     if (e != hipSuccess) return e;
     attr_done = true;
   }
+  hipLaunchKernelGGL((col_kernel<T, M1, LEAN>), grid, dim3(kColThreads), smem, s, a);
+  return hipGetLastError();
+}
+
+template <class T, int M1>
+static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
   constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
   size_t smem = ((size_t)M1 + (size_t)a.ub * GMAX * lds_len(M1)) * sizeof(cplx<T>);
   dim3 grid(a.nslots * (a.M2 / a.g));
-  hipLaunchKernelGGL((col_kernel<T, M1>), grid, dim3(kColThreads), smem, s, a);
-  return hipGetLastError();
+  if (a.lean) return launch_col_v<T, M1, true>(a, s, smem, grid);
+  return launch_col_v<T, M1, false>(a, s, smem, grid);
 }
 
 template <class T>
@@ -572,7 +654,7 @@ int col_batch(int prec, int M1, int u, int nworkgroups) {
   if (ub > u) ub = u < 1 ? 1 : u;
   // a launch that already fills the GPU gains more from occupancy (small LDS
   // per workgroup) than from transforming several columns per workgroup
-  if (nworkgroups >= 512) ub = 1;
+  if (nworkgroups >= kLeanWorkgroups) ub = 1;
   return (int)ub;
 }
 
