@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -235,7 +236,18 @@ struct agg_plan {
   bool plain = false;
   std::vector<agg_plan*> subs;
   double *k1p = nullptr, *k2p = nullptr, *ntp = nullptr;
+  // captured time loop: kGraphSteps Heun steps for one (state pointer, step)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* g_state = nullptr;
+  double g_dt = 0.0;
+  bool graphs = true;
 };
+
+// Heun steps per captured graph of the time loop.
+constexpr int64_t kGraphSteps = 16;
+
+static void drop_graph(agg_plan* p);
 
 extern "C" {
 
@@ -272,6 +284,10 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   p->batch = batch;
   p->stream = (hipStream_t)hip_stream;
   p->trivial = p->tab.u == 0;
+  {
+    const char* ng = std::getenv("AGG_NO_GRAPH");
+    p->graphs = !(ng && ng[0] == '1');
+  }
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
   if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
   if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
@@ -337,13 +353,16 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
 agg_status agg_plan_destroy(agg_plan* p) {
   if (!p) return AGG_OK;
   (void)hipStreamSynchronize(p->stream);
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (agg_plan* sub : p->subs) agg_plan_destroy(sub);
   p->arena.release();
   delete p;
   return AGG_OK;
 }
 
-static agg_status run(agg_plan* p, int mode, double dt, double* state, double* outp, bool row) {
+static agg_status run_on(agg_plan* p, hipStream_t stream, int mode, double dt, double* state, double* outp,
+                         bool row) {
   LaunchArgs a = base_args(p->tab, p->st, nullptr, p->batch);
   a.base = p->base;
   a.stride = p->stride;
@@ -351,8 +370,59 @@ static agg_status run(agg_plan* p, int mode, double dt, double* state, double* o
   a.dt = dt;
   a.ext_state = state;
   a.ext_out = outp;
-  hipError_t e = row ? launch_row(p->tab.prec, a, p->stream) : launch_col(p->tab.prec, a, p->stream);
+  hipError_t e = row ? launch_row(p->tab.prec, a, stream) : launch_col(p->tab.prec, a, stream);
   if (e != hipSuccess) return hip_fail(e, row ? "row pass launch" : "column pass launch");
+  return AGG_OK;
+}
+
+static agg_status run(agg_plan* p, int mode, double dt, double* state, double* outp, bool row) {
+  return run_on(p, p->stream, mode, dt, state, outp, row);
+}
+
+// One full Heun step (stage 1 and stage 2, the latter starting the next step's
+// forward pass) enqueued on `stream`.
+static agg_status full_step(agg_plan* p, hipStream_t stream, double* n, double h) {
+  agg_status rc;
+  if ((rc = run_on(p, stream, CM_H1, h, n, nullptr, true))) return rc;
+  if ((rc = run_on(p, stream, CM_H1, h, n, nullptr, false))) return rc;
+  if ((rc = run_on(p, stream, CM_H2, h, n, nullptr, true))) return rc;
+  return run_on(p, stream, CM_H2_FWD, h, n, nullptr, false);
+}
+
+static void drop_graph(agg_plan* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  p->gexec = nullptr;
+  p->g_state = nullptr;
+}
+
+// The graph of kGraphSteps full steps for (n, h), captured on a private stream
+// (the plan's stream may be the null stream, which cannot be captured) and
+// replayed on the plan's stream.  It holds kernel nodes only.
+static agg_status step_graph(agg_plan* p, double* n, double h) {
+  if (p->gexec && p->g_state == n && p->g_dt == h) return AGG_OK;
+  drop_graph(p);
+  hipError_t e = hipSuccess;
+  if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  agg_status rc = AGG_OK;
+  for (int64_t k = 0; k < kGraphSteps && rc == AGG_OK; ++k) rc = full_step(p, p->cap_stream, n, h);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &graph);
+  if (rc != AGG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    p->gexec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  p->g_state = n;
+  p->g_dt = h;
   return AGG_OK;
 }
 
@@ -400,14 +470,28 @@ static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, 
     return AGG_OK;
   }
   if ((rc = run(p, CM_FWD, 0.0, n, nullptr, false))) return rc;
-  for (int64_t s = 0; s < nsteps; ++s) {
-    double h = (s == nsteps - 1) ? last_dt : dt;
-    if ((rc = run(p, CM_H1, h, n, nullptr, true))) return rc;
-    if ((rc = run(p, CM_H1, h, n, nullptr, false))) return rc;
-    if ((rc = run(p, CM_H2, h, n, nullptr, true))) return rc;
-    if ((rc = run(p, s == nsteps - 1 ? CM_H2 : CM_H2_FWD, h, n, nullptr, false))) return rc;
+  // steps 0..nsteps-2 are full steps with dt; the last one (last_dt) does not
+  // start another forward pass.  Step 0 runs directly (it also sets the kernel
+  // attributes outside any capture); then whole graphs of kGraphSteps steps.
+  const int64_t full = nsteps - 1;
+  int64_t s = 0;
+  if (full > 0) {
+    if ((rc = full_step(p, p->stream, n, dt))) return rc;
+    s = 1;
   }
-  return AGG_OK;
+  if (p->graphs && full - s >= kGraphSteps) {
+    if ((rc = step_graph(p, n, dt))) return rc;
+    for (; s + kGraphSteps <= full; s += kGraphSteps) {
+      hipError_t e = hipGraphLaunch(p->gexec, p->stream);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+  }
+  for (; s < full; ++s)
+    if ((rc = full_step(p, p->stream, n, dt))) return rc;
+  if ((rc = run(p, CM_H1, last_dt, n, nullptr, true))) return rc;
+  if ((rc = run(p, CM_H1, last_dt, n, nullptr, false))) return rc;
+  if ((rc = run(p, CM_H2, last_dt, n, nullptr, true))) return rc;
+  return run(p, CM_H2, last_dt, n, nullptr, false);
 }
 
 agg_status agg_rk2_step(agg_plan* p, double* n, double dt) {

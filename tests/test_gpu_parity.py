@@ -259,3 +259,22 @@ def test_plain_path_matches_oracle_and_shared_path(prec):
     agg.Plan(D, N, k, prec).solve(b, 1e-3, 5e-3)
     torch.cuda.synchronize()
     assert rel(a.cpu().numpy(), b.cpu().numpy()) <= (1e-13 if prec == "fp64" else 1e-11)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_graph_replayed_time_loop_equals_eager_steps(prec):
+    """agg_solve replays captured graphs of the time loop; every replay, with
+    eager work in between, must equal the same steps launched one by one."""
+    D, N, dt = 4, 1000, 1e-3
+    k = synth.kernel_ballistic(D, N, 0.3)
+    plan = agg.Plan(D, N, k, prec)
+    a = torch.empty(N, dtype=torch.float64, device=DEV)
+    for trial in range(3):
+        n0 = synth.n0_random_dense(N, 70 + trial, decay=0.01)
+        a.copy_(torch.tensor(n0, device=DEV))          # same tensor: the cached graph is replayed
+        plan.solve(a, dt, 40 * dt, stats=False)        # 1 direct step, 2 graphs of 16, 6 direct + last
+        b = torch.tensor(n0, device=DEV)
+        for _ in range(40):
+            plan.rk2_step(b, dt)                       # eager launches
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), f"trial {trial}"
