@@ -87,29 +87,26 @@ static double factorial(int d) {
   return f;
 }
 
-agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st) {
-  agg_status rc;
-  st->tab = &T;
-  const int64_t N = T.N;
-  // distinct columns
-  std::vector<double> cols((size_t)T.u * N);
-  for (int c = 0; c < T.u; ++c) std::memcpy(&cols[(size_t)c * N], T.ucols[c].data(), sizeof(double) * N);
-  if ((rc = arena.alloc(cols.size() * 8, (void**)&st->cols))) return rc;
-  if ((rc = upload(st->cols, cols.data(), cols.size() * 8, s))) return rc;
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-  // term tables
+// Host image of everything a kernel set shares between the states using it
+// (distinct columns, term tables, coefficients, twiddles), laid out for one
+// upload; offsets are 256-byte aligned.
+SharedImage make_shared_image(const PlanTables& T) {
+  SharedImage im;
+  const int64_t N = T.N;
   std::vector<int> p_off{0}, p_ids, q_off{0}, q_ids, q_km;
-  std::vector<double> p_coef, q_coef;
+  std::vector<double> coef;
   for (size_t t = 0; t < T.p_ids.size(); ++t) {
     for (int id : T.p_ids[t]) p_ids.push_back(id);
     p_off.push_back((int)p_ids.size());
-    p_coef.push_back((double)T.p_mult[t] / factorial((int)T.p_ids[t].size()));
+    coef.push_back((double)T.p_mult[t] / factorial((int)T.p_ids[t].size()));
   }
   for (size_t t = 0; t < T.q_ids.size(); ++t) {
     for (int id : T.q_ids[t]) q_ids.push_back(id);
     q_off.push_back((int)q_ids.size());
     q_km.push_back(T.q_kmode[t]);
-    q_coef.push_back((double)T.q_mult[t] / factorial(T.q_d[t] - 1));
+    coef.push_back((double)T.q_mult[t] / factorial(T.q_d[t] - 1));
   }
   std::vector<int> blob;
   auto put = [&](const std::vector<int>& v) {
@@ -118,43 +115,61 @@ agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, 
     return off;
   };
   put(p_off);
-  st->o_pids = put(p_ids);
-  st->o_qoff = put(q_off);
-  st->o_qids = put(q_ids);
-  st->o_qkm = put(q_km);
-  st->ntab = (int)blob.size();
-  void* dints;
-  if ((rc = arena.alloc(blob.size() * 4, &dints))) return rc;
-  if ((rc = upload(dints, blob.data(), blob.size() * 4, s))) return rc;
-  st->tabs = (const int*)dints;
-  std::vector<double> coefs(p_coef);
-  coefs.insert(coefs.end(), q_coef.begin(), q_coef.end());
-  void* dco;
-  if ((rc = arena.alloc(std::max<size_t>(coefs.size(), 1) * 8, &dco))) return rc;
-  if ((rc = upload(dco, coefs.data(), coefs.size() * 8, s))) return rc;
-  st->coef = (const double*)dco;
-  st->Tp = (int)p_coef.size();
-  st->Tq = (int)q_coef.size();
+  im.o_pids = put(p_ids);
+  im.o_qoff = put(q_off);
+  im.o_qids = put(q_ids);
+  im.o_qkm = put(q_km);
+  im.ntab = (int)blob.size();
+  im.Tp = (int)T.p_ids.size();
+  im.Tq = (int)T.q_ids.size();
 
-  // twiddles: w_{M1}, w_{M2}, and the two-level table of w_L
-  const int64_t L = T.L;
-  const int64_t nlo = int64_t(1) << T.b, nhi = L >> T.b;
-  std::vector<double> w1(2 * T.M1), w2(2 * T.M2), wl(2 * L), wlo(2 * nlo), whi(2 * nhi);
+  // twiddles: w_{M1}, w_{M2}, and the two halves of the two-level table of w_L
+  const int64_t L = T.L, nlo = int64_t(1) << T.b, nhi = L >> T.b;
+  std::vector<double> w1(2 * T.M1), w2(2 * T.M2), wlo(2 * nlo), whi(2 * nhi);
   twiddle_table(T.M1, w1.data());
   twiddle_table(T.M2, w2.data());
-  twiddle_table(L, wl.data());
-  for (int64_t a = 0; a < nlo; ++a) { wlo[2 * a] = wl[2 * a]; wlo[2 * a + 1] = wl[2 * a + 1]; }
-  for (int64_t a = 0; a < nhi; ++a) {
-    whi[2 * a] = wl[2 * (a << T.b)];
-    whi[2 * a + 1] = wl[2 * (a << T.b) + 1];
-  }
-  const std::vector<double>* srcs[4] = {&w1, &w2, &wlo, &whi};
-  void** dsts[4] = {&st->twP1, &st->twP2, &st->twLlo, &st->twLhi};
-  for (int i = 0; i < 4; ++i) {
-    std::vector<unsigned char> b = twiddle_bytes(T.prec, *srcs[i]);
-    if ((rc = arena.alloc(b.size(), dsts[i]))) return rc;
-    if ((rc = upload(*dsts[i], b.data(), b.size(), s))) return rc;
-  }
+  for (int64_t a = 0; a < nlo; ++a) twiddle_at(L, a, &wlo[2 * a], &wlo[2 * a + 1]);
+  for (int64_t a = 0; a < nhi; ++a) twiddle_at(L, a << T.b, &whi[2 * a], &whi[2 * a + 1]);
+  std::vector<unsigned char> tw[4] = {twiddle_bytes(T.prec, w1), twiddle_bytes(T.prec, w2),
+                                      twiddle_bytes(T.prec, wlo), twiddle_bytes(T.prec, whi)};
+
+  size_t off = 0;
+  im.o_cols = off; off = align256(off + (size_t)T.u * N * 8);
+  im.o_tabs = off; off = align256(off + std::max<size_t>(blob.size(), 1) * 4);
+  im.o_coef = off; off = align256(off + std::max<size_t>(coef.size(), 1) * 8);
+  size_t* two[4] = {&im.o_tw1, &im.o_tw2, &im.o_twlo, &im.o_twhi};
+  for (int i = 0; i < 4; ++i) { *two[i] = off; off = align256(off + tw[i].size()); }
+  im.bytes.assign(off, 0);
+  for (int c = 0; c < T.u; ++c)
+    std::memcpy(&im.bytes[im.o_cols + (size_t)c * N * 8], T.ucols[c].data(), sizeof(double) * N);
+  if (!blob.empty()) std::memcpy(&im.bytes[im.o_tabs], blob.data(), blob.size() * 4);
+  if (!coef.empty()) std::memcpy(&im.bytes[im.o_coef], coef.data(), coef.size() * 8);
+  for (int i = 0; i < 4; ++i) std::memcpy(&im.bytes[*two[i]], tw[i].data(), tw[i].size());
+  return im;
+}
+
+// Device pointers of a shared image uploaded at dev.
+void bind_shared(const SharedImage& im, void* dev, SharedTables* st) {
+  char* b = (char*)dev;
+  st->cols = (double*)(b + im.o_cols);
+  st->tabs = (const int*)(b + im.o_tabs);
+  st->coef = (const double*)(b + im.o_coef);
+  st->twP1 = b + im.o_tw1;
+  st->twP2 = b + im.o_tw2;
+  st->twLlo = b + im.o_twlo;
+  st->twLhi = b + im.o_twhi;
+  st->Tp = im.Tp; st->Tq = im.Tq; st->ntab = im.ntab;
+  st->o_pids = im.o_pids; st->o_qoff = im.o_qoff; st->o_qids = im.o_qids; st->o_qkm = im.o_qkm;
+}
+
+agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st) {
+  agg_status rc;
+  st->tab = &T;
+  SharedImage im = make_shared_image(T);
+  void* dev;
+  if ((rc = arena.alloc(im.bytes.size(), &dev))) return rc;
+  if ((rc = upload(dev, im.bytes.data(), im.bytes.size(), s))) return rc;
+  bind_shared(im, dev, st);
   return AGG_OK;
 }
 

@@ -10,6 +10,15 @@
 // computes exactly what it would compute alone: nothing in a slot's arithmetic
 // depends on its neighbours.  Requests that arrive while others run join at
 // the next tick; finished slots are copied out and their memory returned.
+//
+// Memory: the engine owns one device region (its budget) and one pinned host
+// region, each carved by a first-fit allocator.  A request holds one
+// contiguous device block (tables, state, Heun vectors, spectra) and one
+// pinned host block (tables and initial state staged for upload, then the
+// result).  The tables are built and staged by the submitting thread; at
+// admission the scheduler enqueues a single asynchronous copy on its stream,
+// ordered before the request's first launch.  Admission therefore allocates
+// nothing from the runtime and never waits on the device.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -36,20 +45,90 @@ static double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// First-fit allocator over one region; freed neighbours are merged.
+struct Pool {
+  size_t size = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  void init(size_t s) {
+    size = s;
+    free_.clear();
+    if (s) free_[0] = s;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = align256(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      size_t rem = it->second - n, o2 = it->first + n;
+      free_.erase(it);
+      if (rem) free_[o2] = rem;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align256(n);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+// Byte offsets inside a request's device block:
+//   [tables | n | k1 | n~ | G | dots | V | Z1]
+// The host block mirrors [tables | n] for the single upload, then holds the
+// result.
+struct ReqLayout {
+  size_t o_n = 0, o_k1 = 0, o_nt = 0, o_G = 0, o_dots = 0, o_V = 0, o_Z1 = 0, dev_total = 0;
+  size_t upload = 0, o_out = 0, host_total = 0;
+};
+
+static ReqLayout request_layout(const PlanTables& T, size_t image_bytes) {
+  ReqLayout l;
+  size_t cs = complex_bytes(T.prec), ngroups = T.M2 / T.g, nb = (size_t)T.N * 8;
+  size_t off = align256(image_bytes);
+  l.o_n = off; off = align256(off + nb);
+  l.o_k1 = off; off = align256(off + nb);
+  l.o_nt = off; off = align256(off + nb);
+  l.o_G = off; off = align256(off + (size_t)std::max(T.u, 1) * 8);
+  l.o_dots = off; off = align256(off + (size_t)T.u * ngroups * 8);
+  l.o_V = off; off = align256(off + (size_t)T.M * cs);
+  l.o_Z1 = off; off = align256(off + (size_t)T.u * T.M * cs);
+  l.dev_total = off;
+  l.upload = l.o_n + nb;
+  l.o_out = align256(l.upload);
+  l.host_total = l.o_out + nb;
+  return l;
+}
+
 struct Request {
   uint64_t ticket = 0;
   PlanTables tab;
-  std::vector<double> n0;
+  SharedImage im;                   // offsets of the tables inside the image
+  ReqLayout lay;
+  std::vector<double> staged;       // tables + n0 when no pinned block was free at submit
+  std::atomic<bool> ready{false};   // staging written by the submitter
   double dt = 0, last_dt = 0;
   int64_t nsteps = 0;
   double t_submit = 0, t_admit = -1, t_finish = -1;
-  size_t footprint = 0;
+  bool has_host = false, has_dev = false;
+  size_t host_off = 0, dev_off = 0;
   // device side (valid while admitted)
-  DeviceArena arena;
   SharedTables st;
   SlotDesc sd;
-  double* d_n = nullptr;
-  double* h_out = nullptr;          // pinned result buffer
+  const double* h_out = nullptr;    // pinned result buffer (inside the host block)
   hipEvent_t done_ev = nullptr;
   int64_t stage = 0;                // 0: forward pass pending; 2s+1: stage 1 of step s; 2s+2: stage 2
   int status = AGG_PENDING;
@@ -60,10 +139,9 @@ using BucketKey = std::tuple<int64_t, int, int, int, int>;   // L, M1, M2, g, pr
 
 struct Engine {
   agg_engine_config cfg{};
-  hipStream_t stream = nullptr;      // all kernels and result copies
-  hipStream_t up_stream = nullptr;   // admission uploads (synchronised per upload)
+  hipStream_t stream = nullptr;      // uploads, kernels and result copies
   std::thread worker;
-  std::mutex mu;
+  std::mutex mu;                     // queue, done, known, stop
   std::condition_variable cv;
   bool stop = false;
   uint64_t next_ticket = 1;
@@ -73,6 +151,16 @@ struct Engine {
   std::unordered_map<uint64_t, std::unique_ptr<Request>> done;
   std::unordered_map<uint64_t, int> known;                    // ticket -> 1 while not polled
   std::atomic<int64_t> n_completed{0}, bytes_in_use{0}, n_active{0};
+  // regions: the device pool is used by the scheduler only; the host pool is
+  // shared with submitting threads under mu.  Queued requests that hold a
+  // pinned block always form a prefix of the queue (a submitter takes one only
+  // while no queued request is staged in pageable memory), so the head of the
+  // queue can always get its block once the running requests retire.
+  char* dev_base = nullptr;
+  char* host_base = nullptr;
+  Pool dev, host;
+  int64_t n_staged = 0;
+  std::vector<hipEvent_t> spare_events;
   // descriptor staging ring (pinned host -> device), one entry per tick
   static constexpr int kRing = 8;
   SlotDesc* h_desc[kRing] = {nullptr};
@@ -81,74 +169,105 @@ struct Engine {
   bool ring_used[kRing] = {false};
   int ring_pos = 0;
   int cap_slots = 256;
-  std::string init_error;
-  int init_status = AGG_OK;
 
   void run();
   void admit();
   void tick();
   void retire(bool block);
-  agg_status setup_device(Request& r);
+  bool take_host(Request& r);
+  bool setup_device(Request& r);
+  void release(Request& r);
 };
 
-agg_status Engine::setup_device(Request& r) {
-  agg_status rc;
-  if ((rc = build_shared(r.tab, up_stream, r.arena, &r.st))) return rc;
-  if ((rc = build_slot(r.tab, r.st, r.arena, &r.sd))) return rc;
-  if ((rc = r.arena.alloc(sizeof(double) * r.tab.N, (void**)&r.d_n))) return rc;
-  if ((rc = upload(r.d_n, r.n0.data(), sizeof(double) * r.tab.N, up_stream))) return rc;
-  r.sd.n_state = r.d_n;
-  hipError_t e = hipHostMalloc((void**)&r.h_out, sizeof(double) * r.tab.N, hipHostMallocDefault);
-  if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
-  e = hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming);
-  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-  return AGG_OK;
+// Gives a request that was staged in pageable memory its pinned block.
+bool Engine::take_host(Request& r) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!host.alloc(r.lay.host_total, &r.host_off)) return false;
+    --n_staged;
+  }
+  r.has_host = true;
+  std::memcpy(host_base + r.host_off, r.staged.data(), r.lay.upload);
+  std::vector<double>().swap(r.staged);
+  return true;
 }
 
-static void release_device(Request& r) {
-  r.arena.release();
-  if (r.h_out) { (void)hipHostFree(r.h_out); r.h_out = nullptr; }
-  if (r.done_ev) { (void)hipEventDestroy(r.done_ev); r.done_ev = nullptr; }
+// Reserves the device block, enqueues the upload and fills the slot
+// descriptor; false if a pool is full (a pinned block already taken is kept).
+bool Engine::setup_device(Request& r) {
+  if (!r.has_host && !take_host(r)) return false;
+  if (!dev.alloc(r.lay.dev_total, &r.dev_off)) return false;
+  r.has_dev = true;
+  char* d = dev_base + r.dev_off;
+  const char* h = host_base + r.host_off;
+  (void)hipMemcpyAsync(d, h, r.lay.upload, hipMemcpyHostToDevice, stream);
+  r.h_out = (const double*)(h + r.lay.o_out);
+  bind_shared(r.im, d, &r.st);
+  r.st.tab = &r.tab;
+  SlotDesc& s = r.sd;
+  std::memset((void*)&s, 0, sizeof(s));
+  s.n_state = (double*)(d + r.lay.o_n);
+  s.k1 = (double*)(d + r.lay.o_k1);
+  s.ntil = (double*)(d + r.lay.o_nt);
+  s.G = (double*)(d + r.lay.o_G);
+  s.dots = (double*)(d + r.lay.o_dots);
+  s.V = d + r.lay.o_V;
+  s.Z1 = d + r.lay.o_Z1;
+  s.cols = r.st.cols;
+  s.tab = r.st.tabs;
+  s.coef = r.st.coef;
+  s.ntab = r.st.ntab;
+  s.o_pids = r.st.o_pids; s.o_qoff = r.st.o_qoff; s.o_qids = r.st.o_qids; s.o_qkm = r.st.o_qkm;
+  s.N = (int)r.tab.N; s.u = r.tab.u; s.Tp = r.st.Tp; s.Tq = r.st.Tq;
+  if (!spare_events.empty()) {
+    r.done_ev = spare_events.back();
+    spare_events.pop_back();
+  } else if (hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming) != hipSuccess) {
+    r.done_ev = nullptr;
+    r.status = AGG_EHIP;
+  }
+  return true;
+}
+
+void Engine::release(Request& r) {
+  if (r.has_dev) dev.release(r.dev_off, r.lay.dev_total);
+  if (r.has_host) {
+    std::lock_guard<std::mutex> lk(mu);
+    host.release(r.host_off, r.lay.host_total);
+  }
+  r.has_dev = r.has_host = false;
+  r.h_out = nullptr;
+  if (r.done_ev) spare_events.push_back(r.done_ev);
+  r.done_ev = nullptr;
 }
 
 void Engine::admit() {
-  std::vector<std::unique_ptr<Request>> take;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    int64_t budget = cfg.mem_budget;
-    int64_t used = bytes_in_use.load();
-    while (!queue.empty()) {
-      Request& r = *queue.front();
-      if ((int)(running.size() + take.size()) >= cap_slots) break;
-      if (used + (int64_t)r.footprint > budget) break;     // FIFO: no overtaking
-      used += (int64_t)r.footprint;
-      take.push_back(std::move(queue.front()));
+  for (;;) {
+    Request* r;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (queue.empty() || (int)running.size() >= cap_slots) return;
+      r = queue.front().get();      // only this thread pops: r stays valid unlocked
+      if (!r->ready.load(std::memory_order_acquire)) return;
+    }
+    if (r->nsteps > 0 && !setup_device(*r)) return;     // FIFO: no overtaking
+    std::unique_ptr<Request> rp;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      rp = std::move(queue.front());
       queue.pop_front();
     }
-  }
-  for (auto& rp : take) {
-    Request& r = *rp;
-    r.t_admit = now_s();
-    if (r.nsteps == 0) {                // nothing to integrate
-      r.result = r.n0;
-      r.status = AGG_OK;
-      r.t_finish = now_s();
+    r->t_admit = now_s();
+    if (r->nsteps == 0 || r->status != AGG_PENDING) {   // nothing to integrate, or no event
+      if (r->status == AGG_PENDING) r->status = AGG_OK;
+      r->t_finish = now_s();
+      release(*r);
       std::lock_guard<std::mutex> lk(mu);
       n_completed++;
-      done[r.ticket] = std::move(rp);
+      done[r->ticket] = std::move(rp);
       continue;
     }
-    agg_status rc = setup_device(r);
-    if (rc != AGG_OK) {
-      release_device(r);
-      r.status = rc;
-      r.t_finish = now_s();
-      std::lock_guard<std::mutex> lk(mu);
-      n_completed++;
-      done[r.ticket] = std::move(rp);
-      continue;
-    }
-    bytes_in_use += (int64_t)r.footprint;
+    bytes_in_use += (int64_t)r->lay.dev_total;
     n_active++;
     running.push_back(std::move(rp));
   }
@@ -168,10 +287,11 @@ void Engine::tick() {
     const PlanTables& T = rp->tab;
     buckets[BucketKey(T.L, T.M1, T.M2, T.g, T.prec)].push_back(rp.get());
   }
+  struct Launch { int off, cnt, umax, tab_max, coef_max; Request* first; };
+  std::vector<Launch> launches;
   int base = 0;
-  std::vector<std::tuple<int, int, Request*>> launches;   // (base, count, first)
   for (auto& kv : buckets) {
-    int cnt = 0;
+    Launch L{base, 0, 1, 0, 0, kv.second.front()};
     for (Request* r : kv.second) {
       SlotDesc s = r->sd;
       if (r->stage == 0) {
@@ -183,40 +303,36 @@ void Engine::tick() {
         s.dt = step == r->nsteps - 1 ? r->last_dt : r->dt;
         s.mode = st1 ? CM_H1 : (step == r->nsteps - 1 ? CM_H2 : CM_H2_FWD);
       }
-      hd[base + cnt] = s;
-      ++cnt;
+      hd[base + L.cnt] = s;
+      L.umax = std::max(L.umax, r->tab.u);
+      L.tab_max = std::max(L.tab_max, r->st.ntab);
+      L.coef_max = std::max(L.coef_max, r->st.Tp + r->st.Tq);
+      ++L.cnt;
     }
-    launches.emplace_back(base, cnt, kv.second.front());
-    base += cnt;
+    launches.push_back(L);
+    base += L.cnt;
   }
   hipError_t e = hipMemcpyAsync(dd, hd, sizeof(SlotDesc) * base, hipMemcpyHostToDevice, stream);
   for (size_t b = 0; b < launches.size() && e == hipSuccess; ++b) {
-    int off = std::get<0>(launches[b]), cnt = std::get<1>(launches[b]);
-    Request* first = std::get<2>(launches[b]);
-    LaunchArgs a = base_args(first->tab, first->st, dd + off, cnt);
+    const Launch& L = launches[b];
+    const PlanTables& T = L.first->tab;
+    // every slot of a bucket has identical twiddle tables: take the first's
+    LaunchArgs a = base_args(T, L.first->st, dd + L.off, L.cnt);
+    int nwg = L.cnt * (T.M2 / T.g);
     a.mode = -1;
-    int umax = 1, tpm = 0, tidm = 0;
-    for (int i = 0; i < cnt; ++i) umax = std::max(umax, hd[off + i].u);
-    for (auto& kv2 : buckets)
-      for (Request* r : kv2.second)
-        if (r->tab.L == first->tab.L && r->tab.M1 == first->tab.M1 && r->tab.M2 == first->tab.M2 &&
-            r->tab.g == first->tab.g && r->tab.prec == first->tab.prec) {
-          tpm = std::max(tpm, r->st.ntab);
-          tidm = std::max(tidm, r->st.Tp + r->st.Tq);
-        }
-    a.umax = umax;
-    a.ub = col_batch(first->tab.prec, first->tab.M1, umax, cnt * (first->tab.M2 / first->tab.g));
-    a.lean = cnt * (first->tab.M2 / first->tab.g) >= kLeanWorkgroups ? 1 : 0;
-    a.tab_max = tpm;
-    a.coef_max = tidm;
-    e = launch_row(first->tab.prec, a, stream);
-    if (e == hipSuccess) e = launch_col(first->tab.prec, a, stream);
+    a.umax = L.umax;
+    a.ub = col_batch(T.prec, T.M1, L.umax, nwg);
+    a.lean = nwg >= kLeanWorkgroups ? 1 : 0;
+    a.tab_max = L.tab_max;
+    a.coef_max = L.coef_max;
+    e = launch_row(T.prec, a, stream);
+    if (e == hipSuccess) e = launch_col(T.prec, a, stream);
   }
   if (e == hipSuccess) e = hipEventRecord(ring_ev[slot_ring], stream);
   ring_used[slot_ring] = true;
   if (e != hipSuccess) {
     // a failed launch poisons every running request of this tick
-    for (auto& rp : running) { rp->status = AGG_EHIP; }
+    for (auto& rp : running) rp->status = AGG_EHIP;
   }
 
   // advance stages; requests whose last stage was just enqueued copy out
@@ -226,7 +342,8 @@ void Engine::tick() {
     r.stage++;
     bool last = r.stage == 2 * r.nsteps + 1 || r.status == AGG_EHIP;
     if (last) {
-      (void)hipMemcpyAsync(r.h_out, r.d_n, sizeof(double) * r.tab.N, hipMemcpyDeviceToHost, stream);
+      (void)hipMemcpyAsync((void*)r.h_out, r.sd.n_state, sizeof(double) * r.tab.N, hipMemcpyDeviceToHost,
+                           stream);
       (void)hipEventRecord(r.done_ev, stream);
       finishing.push_back(std::move(rp));
     } else {
@@ -249,9 +366,9 @@ void Engine::retire(bool block) {
       for (double v : r.result) if (!std::isfinite(v)) { r.status = AGG_ENONFINITE; break; }
     }
     if (q != hipSuccess) r.status = AGG_EHIP;
-    release_device(r);
-    bytes_in_use -= (int64_t)r.footprint;
+    bytes_in_use -= (int64_t)r.lay.dev_total;
     n_active--;
+    release(r);
     std::lock_guard<std::mutex> lk(mu);
     n_completed++;
     done[r.ticket] = std::move(rp);
@@ -276,9 +393,8 @@ void Engine::run() {
     retire(idle_launches && !finishing.empty());
   }
   (void)hipStreamSynchronize(stream);
-  (void)hipStreamSynchronize(up_stream);
   for (auto* v : {&running, &finishing})
-    for (auto& rp : *v) release_device(*rp);
+    for (auto& rp : *v) release(*rp);
 }
 
 }  // namespace agg
@@ -288,6 +404,19 @@ using namespace agg;
 struct agg_engine {
   Engine eng;
 };
+
+static void engine_free(Engine& g) {
+  for (int i = 0; i < Engine::kRing; ++i) {
+    if (g.h_desc[i]) (void)hipHostFree(g.h_desc[i]);
+    if (g.d_desc[i]) (void)hipFree(g.d_desc[i]);
+    if (g.ring_ev[i]) (void)hipEventDestroy(g.ring_ev[i]);
+  }
+  for (hipEvent_t ev : g.spare_events) (void)hipEventDestroy(ev);
+  g.spare_events.clear();
+  if (g.dev_base) (void)hipFree(g.dev_base);
+  if (g.host_base) (void)hipHostFree(g.host_base);
+  if (g.stream) (void)hipStreamDestroy(g.stream);
+}
 
 extern "C" {
 
@@ -303,30 +432,32 @@ agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out) {
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
   if (c.device < 0 || c.device >= ndev) return set_error(AGG_EINVAL, "no such device");
+  // pinned staging: a quarter of the device budget, between 64 MiB and 2 GiB
+  int64_t host_bytes = std::min<int64_t>(std::max<int64_t>(c.mem_budget / 4, int64_t(64) << 20),
+                                         int64_t(2) << 30);
   agg_engine* E = new agg_engine();
   Engine& g = E->eng;
   g.cfg = c;
   g.cap_slots = c.max_slots;
   e = hipSetDevice(c.device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.up_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void**)&g.dev_base, (size_t)c.mem_budget);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&g.host_base, (size_t)host_bytes, hipHostMallocDefault);
   for (int i = 0; i < Engine::kRing && e == hipSuccess; ++i) {
     e = hipHostMalloc((void**)&g.h_desc[i], sizeof(SlotDesc) * c.max_slots, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&g.d_desc[i], sizeof(SlotDesc) * c.max_slots);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ring_ev[i], hipEventDisableTiming);
   }
   if (e != hipSuccess) {
-    agg_status rc = hip_fail(e, "engine setup");
-    for (int i = 0; i < Engine::kRing; ++i) {
-      if (g.h_desc[i]) (void)hipHostFree(g.h_desc[i]);
-      if (g.d_desc[i]) (void)hipFree(g.d_desc[i]);
-      if (g.ring_ev[i]) (void)hipEventDestroy(g.ring_ev[i]);
-    }
-    if (g.stream) (void)hipStreamDestroy(g.stream);
-    if (g.up_stream) (void)hipStreamDestroy(g.up_stream);
+    agg_status rc = (e == hipErrorOutOfMemory) ? set_error(AGG_ENOMEM, "engine memory could not be reserved")
+                                               : hip_fail(e, "engine setup");
+    (void)hipGetLastError();
+    engine_free(g);
     delete E;
     return rc;
   }
+  g.dev.init((size_t)c.mem_budget);
+  g.host.init((size_t)host_bytes);
   g.worker = std::thread([&g] { g.run(); });
   *out = E;
   return AGG_OK;
@@ -341,13 +472,7 @@ agg_status agg_engine_destroy(agg_engine* E) {
   }
   g.cv.notify_all();
   if (g.worker.joinable()) g.worker.join();
-  for (int i = 0; i < Engine::kRing; ++i) {
-    if (g.h_desc[i]) (void)hipHostFree(g.h_desc[i]);
-    if (g.d_desc[i]) (void)hipFree(g.d_desc[i]);
-    if (g.ring_ev[i]) (void)hipEventDestroy(g.ring_ev[i]);
-  }
-  if (g.stream) (void)hipStreamDestroy(g.stream);
-  if (g.up_stream) (void)hipStreamDestroy(g.up_stream);
+  engine_free(g);
   delete E;
   return AGG_OK;
 }
@@ -364,25 +489,47 @@ agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms
   if (r->tab.u == 0) return set_error(AGG_EINVAL, "the engine needs at least one term with rank > 0");
   for (int64_t i = 0; i < N; ++i)
     if (!std::isfinite(n0[i])) return set_error(AGG_ENONFINITE, "non-finite initial value");
-  r->n0.assign(n0, n0 + N);
   r->dt = dt;
   time_grid(dt, t_end, &r->nsteps, &r->last_dt);
-  // device footprint: state, one slot, shared tables, twiddles (upper bound)
-  const PlanTables& T = r->tab;
-  size_t cs = complex_bytes(T.prec);
-  size_t tw = (size_t)(T.M1 + T.M2 + (int64_t(1) << T.b) + (T.L >> T.b)) * cs;
-  r->footprint = slot_bytes(T) + (size_t)T.N * 8 + (size_t)T.u * T.N * 8 + tw + 64 * 1024;
   Engine& g = E->eng;
-  if ((int64_t)r->footprint > g.cfg.mem_budget)
+  // the tables are built on the caller's thread, off the scheduler's path
+  r->im = make_shared_image(r->tab);
+  r->lay = request_layout(r->tab, r->im.bytes.size());
+  if ((int64_t)r->lay.dev_total > g.cfg.mem_budget || r->lay.host_total > g.host.size)
     return set_error(AGG_ENOMEM, "request footprint exceeds the engine budget");
-  r->t_submit = now_s();
+  const size_t nb = (size_t)N * 8;
+  Request* rr = r.get();
   {
+    // ticket order, queue order and pinned-block order agree
     std::lock_guard<std::mutex> lk(g.mu);
-    r->ticket = g.next_ticket++;
-    *ticket = r->ticket;
-    g.known[r->ticket] = 1;
+    if (rr->nsteps > 0) {
+      if (g.n_staged == 0 && g.host.alloc(rr->lay.host_total, &rr->host_off))
+        rr->has_host = true;
+      else
+        ++g.n_staged;
+    }
+    rr->ticket = g.next_ticket++;
+    *ticket = rr->ticket;
+    rr->t_submit = now_s();
+    g.known[rr->ticket] = 1;
     g.queue.push_back(std::move(r));
   }
+  // staging is written outside the lock; the scheduler waits for `ready`
+  if (rr->nsteps == 0) {
+    rr->result.assign(n0, n0 + N);
+  } else {
+    char* h;
+    if (rr->has_host) {
+      h = g.host_base + rr->host_off;
+    } else {
+      rr->staged.assign(rr->lay.upload / 8 + 1, 0.0);
+      h = (char*)rr->staged.data();
+    }
+    std::memcpy(h, rr->im.bytes.data(), rr->im.bytes.size());
+    std::memcpy(h + rr->lay.o_n, n0, nb);
+  }
+  std::vector<unsigned char>().swap(rr->im.bytes);   // offsets stay, bytes are staged
+  rr->ready.store(true, std::memory_order_release);
   g.cv.notify_all();
   return AGG_OK;
 }

@@ -33,6 +33,15 @@ struct SharedTables {
   void *twP1 = nullptr, *twP2 = nullptr, *twLlo = nullptr, *twLhi = nullptr;
 };
 
+// Host image of the shared tables, laid out for a single upload.
+struct SharedImage {
+  std::vector<unsigned char> bytes;
+  size_t o_cols = 0, o_tabs = 0, o_coef = 0, o_tw1 = 0, o_tw2 = 0, o_twlo = 0, o_twhi = 0;
+  int Tp = 0, Tq = 0, ntab = 0, o_pids = 0, o_qoff = 0, o_qids = 0, o_qkm = 0;
+};
+SharedImage make_shared_image(const PlanTables& T);
+void bind_shared(const SharedImage& im, void* dev, SharedTables* st);
+
 agg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena& arena, int batch,
                        SlotDesc* sd, SlotStride* stride);

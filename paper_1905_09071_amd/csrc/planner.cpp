@@ -147,36 +147,39 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
 // exp(-2 pi i e/P) with exact reduction of e to the first octant, so that the
 // table has the exact symmetries of the roots of unity; cos/sin of the reduced
 // angle are taken in x87 extended precision and rounded once to binary64.
-void twiddle_table(int64_t P, double* out) {
+void twiddle_at(int64_t P, int64_t e, double* re, double* im) {
   const long double two_pi = 6.283185307179586476925286766559005768L;
-  for (int64_t e = 0; e < P; ++e) {
-    double c, s;   // exp(+2 pi i e / P) = c + i s
-    if (P < 8) {
-      static const double tc[4] = {1.0, 0.0, -1.0, 0.0}, ts[4] = {0.0, 1.0, 0.0, -1.0};
-      int64_t q = e * (4 / P);
-      c = tc[q]; s = ts[q];
+  double c, s;   // exp(+2 pi i e / P) = c + i s
+  e %= P;
+  if (P < 8) {
+    static const double tc[4] = {1.0, 0.0, -1.0, 0.0}, ts[4] = {0.0, 1.0, 0.0, -1.0};
+    int64_t q = e * (4 / P);
+    c = tc[q]; s = ts[q];
+  } else {
+    int64_t quarter = P / 4, eighth = P / 8;
+    int64_t q = e / quarter, r = e % quarter;
+    long double cr, sr;
+    if (r <= eighth) {
+      long double a = two_pi * (long double)r / (long double)P;
+      cr = cosl(a); sr = sinl(a);
     } else {
-      int64_t quarter = P / 4, eighth = P / 8;
-      int64_t q = e / quarter, r = e % quarter;
-      long double cr, sr;
-      if (r <= eighth) {
-        long double a = two_pi * (long double)r / (long double)P;
-        cr = cosl(a); sr = sinl(a);
-      } else {
-        long double a = two_pi * (long double)(quarter - r) / (long double)P;
-        cr = sinl(a); sr = cosl(a);
-      }
-      double c0 = (double)cr, s0 = (double)sr;
-      switch (q) {
-        case 0: c = c0; s = s0; break;
-        case 1: c = -s0; s = c0; break;
-        case 2: c = -c0; s = -s0; break;
-        default: c = s0; s = -c0; break;
-      }
+      long double a = two_pi * (long double)(quarter - r) / (long double)P;
+      cr = sinl(a); sr = cosl(a);
     }
-    out[2 * e] = c;
-    out[2 * e + 1] = -s;
+    double c0 = (double)cr, s0 = (double)sr;
+    switch (q) {
+      case 0: c = c0; s = s0; break;
+      case 1: c = -s0; s = c0; break;
+      case 2: c = -c0; s = -s0; break;
+      default: c = s0; s = -c0; break;
+    }
   }
+  *re = c;
+  *im = -s;
+}
+
+void twiddle_table(int64_t P, double* out) {
+  for (int64_t e = 0; e < P; ++e) twiddle_at(P, e, &out[2 * e], &out[2 * e + 1]);
 }
 
 void time_grid(double dt, double t_end, int64_t* nsteps, double* last_dt) {

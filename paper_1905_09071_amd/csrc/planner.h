@@ -35,8 +35,9 @@ struct PlanTables {
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
                       PlanTables* out, std::string* err, bool dedup = true);
 
-// exp(-2 pi i e / P) for e = 0..P-1, interleaved (re, im), binary64.
+// exp(-2 pi i e / P) for e = 0..P-1, interleaved (re, im), binary64; and one entry.
 void twiddle_table(int64_t P, double* out);
+void twiddle_at(int64_t P, int64_t e, double* re, double* im);
 
 // Time grid of a solve: number of steps and the size of the last one.
 void time_grid(double dt, double t_end, int64_t* nsteps, double* last_dt);
