@@ -77,6 +77,44 @@ def measured_traffic(which: int, prec: str):
     return t.get("bytes_per_launch", {}).get(f"{prec}:{which}")
 
 
+def write_traffic(fetch_csv: str, write_csv: str, copy_mib: int, prec: str) -> dict:
+    """Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) of `bench.py --quick --copy-probe MIB` into bytes per launch of the
+    column and row passes, calibrated by the counters of the plain device copy
+    of known size; writes profiles/traffic_c3.json and returns its content."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        out = {}
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == counter:
+                    out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return out
+
+    F, W = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_f = max(max(v) for k, v in F.items() if "copyBuffer" in k)
+    copy_w = max(max(v) for k, v in W.items() if "copyBuffer" in k)
+    fs, ws = copy_mib * 1024.0 / copy_f, copy_mib * 1024.0 / copy_w
+    med, per_launch = {}, {}
+    for k in F:
+        for tag, which in (("agg::col_kernel", 3), ("agg::row_kernel", 1)):
+            if tag in k and k in W:
+                short = k.split("(")[0].replace("void agg::", "")
+                mf, mw = statistics.median(F[k]), statistics.median(W[k])
+                med[short] = {"FETCH_SIZE": mf, "WRITE_SIZE": mw}
+                per_launch[f"{prec}:{which}"] = round(mf * 1024 * fs + mw * 1024 * ws)
+    t = {"workload": f"D=4 N=65536 ballistic a=0.4, one state, {prec}",
+         "kernel_source_hash": kernel_source_hash(), "copy_probe_MiB": copy_mib,
+         "copy_fetch_KiB": copy_f, "copy_write_KiB": copy_w,
+         "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+         "bytes_per_launch": per_launch, "median_KiB_per_dispatch": med}
+    with open(os.path.join(ROOT, "profiles", "traffic_c3.json"), "w") as f:
+        json.dump(t, f, indent=1)
+    return t
+
+
 def time_steps(plan, n, dt, steps, warmup, torch):
     plan.solve(n, dt, warmup * dt, stats=False)
     torch.cuda.synchronize()
@@ -123,7 +161,13 @@ def main():
                     help="profiling aid: time only the primary precision, no pass timing, no other lines")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="profiling aid: also copy a float64 tensor of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn the two counter runs of --quick --copy-probe into profiles/traffic_c3.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        t = write_traffic(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 256, args.prec)
+        print(json.dumps(t))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

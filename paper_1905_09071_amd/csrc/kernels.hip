@@ -15,6 +15,8 @@
 // q_k = -n_k sum_c U_c(k) G_c.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_lds.h"
 #include "kernels.h"
 
@@ -30,16 +32,24 @@ template <> struct StageRadix<ff> { static constexpr int value = 4; };
 // Pointers taken from descriptors and launch structs would otherwise compile
 // to flat (generic) accesses, which also count against the LDS wait counter:
 // every LDS barrier would then wait for all prefetched global loads.
-// Class types (complex values, descriptors) move as 8-byte words.
+// Class types (complex values, descriptors) move as the widest whole words:
+// 16 bytes when the size allows (every buffer and element offset of a 16-byte
+// type is 16-byte aligned), else 8.  Two 8-byte stores per 16-byte element
+// were measured to double the HBM write bytes of a fully coalesced store.
 typedef unsigned int gword __attribute__((ext_vector_type(2)));
+typedef unsigned int gword4 __attribute__((ext_vector_type(4)));
+template <class T> struct GWord {
+  using type = typename std::conditional<sizeof(T) % 16 == 0, gword4, gword>::type;
+  static constexpr int count = sizeof(T) / sizeof(type);
+};
 template <class T> __device__ __forceinline__ T ldg(const T* p) {
   if constexpr (__is_class(T)) {
-    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 4, "8-byte words");
-    constexpr int W = sizeof(T) / 8;
-    gword w[W];
-    const __attribute__((address_space(1))) gword* q = (const __attribute__((address_space(1))) gword*)p;
+    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 4, "whole 8-byte words");
+    using W = typename GWord<T>::type;
+    W w[GWord<T>::count];
+    const __attribute__((address_space(1))) W* q = (const __attribute__((address_space(1))) W*)p;
 #pragma unroll
-    for (int i = 0; i < W; ++i) w[i] = q[i];
+    for (int i = 0; i < GWord<T>::count; ++i) w[i] = q[i];
     T v;
     __builtin_memcpy(&v, w, sizeof(T));
     return v;
@@ -49,13 +59,13 @@ template <class T> __device__ __forceinline__ T ldg(const T* p) {
 }
 template <class T> __device__ __forceinline__ void stg(T* p, T v) {
   if constexpr (__is_class(T)) {
-    static_assert(sizeof(T) % 8 == 0, "8-byte words");
-    constexpr int W = sizeof(T) / 8;
-    gword w[W];
+    static_assert(sizeof(T) % 8 == 0, "whole 8-byte words");
+    using W = typename GWord<T>::type;
+    W w[GWord<T>::count];
     __builtin_memcpy(w, &v, sizeof(T));
-    __attribute__((address_space(1))) gword* q = (__attribute__((address_space(1))) gword*)p;
+    __attribute__((address_space(1))) W* q = (__attribute__((address_space(1))) W*)p;
 #pragma unroll
-    for (int i = 0; i < W; ++i) q[i] = w[i];
+    for (int i = 0; i < GWord<T>::count; ++i) q[i] = w[i];
   } else {
     *(__attribute__((address_space(1))) T*)p = v;
   }
@@ -365,8 +375,8 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
 // LDS: M2 twiddles (global for M2 = 2048, where the rows need the room), the
 // gain-term tables, u*nrows rows, u Nyquist values.
 // ---------------------------------------------------------------------------
-template <class T, int M2>
-__global__ __launch_bounds__(kThreads, M2 <= 512 ? 5 : 1) void row_kernel(LaunchArgs a) {
+template <class T, int M2, bool LEAN>
+__global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs a) {
   constexpr bool TW_LDS = M2 <= 512;
   constexpr int NB = (2048 / M2) > 0 ? 2048 / M2 : 1;
   constexpr int STR = lds_len(M2);
@@ -660,15 +670,22 @@ int col_batch(int prec, int M1, int u, int nworkgroups) {
 
 template <class T, int M2>
 static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s, size_t smem) {
-  static bool attr_done = false;   // raise the dynamic LDS cap once per instantiation
-  if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void*)row_kernel<T, M2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+  // saturating launches trade registers for five resident work groups per CU;
+  // smaller ones keep every register (no spills) for the shortest chains
+  constexpr bool kHasLean = M2 <= 512;
+  const bool lean = kHasLean && (int64_t)a.nslots * (a.M1 / 2 + 1) >= kLeanWorkgroups;
+  const void* fn = lean ? (const void*)row_kernel<T, M2, kHasLean> : (const void*)row_kernel<T, M2, false>;
+  static bool attr_done[2] = {false, false};   // raise the dynamic LDS cap once per instantiation
+  if (!attr_done[lean]) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
     if (e != hipSuccess) return e;
-    attr_done = true;
+    attr_done[lean] = true;
   }
   dim3 grid(a.nslots * (a.M1 / 2 + 1));
-  hipLaunchKernelGGL((row_kernel<T, M2>), grid, dim3(kThreads), smem, s, a);
+  if (lean)
+    hipLaunchKernelGGL((row_kernel<T, M2, kHasLean>), grid, dim3(kThreads), smem, s, a);
+  else
+    hipLaunchKernelGGL((row_kernel<T, M2, false>), grid, dim3(kThreads), smem, s, a);
   return hipGetLastError();
 }
 
