@@ -173,9 +173,11 @@ agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, 
   return AGG_OK;
 }
 
+// Partial dot products are kept for M2 column groups per column: room for any
+// launch-time column group g' <= g (the plan API narrows g for small batches).
 size_t slot_bytes(const PlanTables& T) {
   size_t cs = complex_bytes(T.prec);
-  size_t ngroups = T.M2 / T.g;
+  size_t ngroups = T.M2;
   return (size_t)T.u * T.M * cs + (size_t)T.M * cs + (size_t)T.u * ngroups * 8 + (size_t)T.u * 8 +
          2 * (size_t)T.N * 8;
 }
@@ -186,7 +188,7 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
                        SlotDesc* sd, SlotStride* stride) {
   agg_status rc;
   size_t cs = complex_bytes(T.prec);
-  size_t ngroups = T.M2 / T.g;
+  size_t ngroups = T.M2;
   SlotStride s;
   s.Z1 = (int64_t)((size_t)T.u * T.M * cs);
   s.V = (int64_t)((size_t)T.M * cs);
@@ -213,7 +215,8 @@ agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& 
   return build_slots(T, st, arena, 1, sd, nullptr);
 }
 
-LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots) {
+LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots,
+                     bool spread) {
   LaunchArgs a;
   std::memset((void*)&a, 0, sizeof(a));
   a.slots = d_slots;
@@ -221,11 +224,15 @@ LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc
   a.mode = -1;
   a.twP1 = st.twP1; a.twP2 = st.twP2; a.twLlo = st.twLlo; a.twLhi = st.twLhi;
   a.M1 = T.M1; a.M2 = T.M2; a.g = T.g; a.b = T.b; a.L = T.L;
+  // a launch with fewer column groups than CUs takes narrower groups, so that
+  // every CU holds one (each column is still transformed whole)
+  if (spread)
+    while (a.g > 1 && (int64_t)nslots * (T.M2 / a.g) < kSpreadWorkgroups) a.g >>= 1;
   a.umax = std::max(T.u, 1);
-  a.ub = col_batch(T.prec, T.M1, T.u, nslots * (T.M2 / T.g));
-  a.lean = nslots * (T.M2 / T.g) >= kLeanWorkgroups ? 1 : 0;
+  a.ub = col_batch(T.prec, T.M1, T.u, nslots * (T.M2 / a.g));
+  a.lean = nslots * (T.M2 / a.g) >= kLeanWorkgroups ? 1 : 0;
   a.lgg = 0;
-  while ((1 << a.lgg) < T.g) ++a.lgg;
+  while ((1 << a.lgg) < a.g) ++a.lgg;
   a.tab_max = st.ntab;
   a.coef_max = st.Tp + st.Tq;
   return a;
@@ -378,7 +385,7 @@ agg_status agg_plan_destroy(agg_plan* p) {
 
 static agg_status run_on(agg_plan* p, hipStream_t stream, int mode, double dt, double* state, double* outp,
                          bool row) {
-  LaunchArgs a = base_args(p->tab, p->st, nullptr, p->batch);
+  LaunchArgs a = base_args(p->tab, p->st, nullptr, p->batch, true);
   a.base = p->base;
   a.stride = p->stride;
   a.mode = mode;

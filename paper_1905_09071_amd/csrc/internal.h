@@ -48,7 +48,11 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st);
 agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd);
 size_t slot_bytes(const PlanTables& T);
-LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots);
+// spread: narrow the column group g below the plan's when the launch has fewer
+// column groups than CUs; every launch that shares a slot's partial dot
+// products must be built with the same choice and slot count.
+LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots,
+                     bool spread = false);
 
 // kernels.hip
 hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s);

@@ -375,14 +375,21 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
 // LDS: M2 twiddles (global for M2 = 2048, where the rows need the room), the
 // gain-term tables, u*nrows rows, u Nyquist values.
 // ---------------------------------------------------------------------------
+// Threads per row-pass workgroup: below saturation (about one workgroup per
+// CU) twice the threads halve every per-thread chain of the transforms.
+template <int M2, bool LEAN> struct RowThreads {
+  static constexpr int value = (!LEAN && M2 >= 128) ? 2 * kThreads : kThreads;
+};
+
 template <class T, int M2, bool LEAN>
-__global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs a) {
+__global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void row_kernel(LaunchArgs a) {
+  constexpr int NT = RowThreads<M2, LEAN>::value;
   constexpr bool TW_LDS = M2 <= 512;
   constexpr int NB = (2048 / M2) > 0 ? 2048 / M2 : 1;
   constexpr int STR = lds_len(M2);
-  constexpr int NWAVE = kThreads / 64;
-  constexpr int UPT = (M2 + kThreads - 1) / kThreads;       // combine units per thread
-  constexpr int VPT = (2 * M2 + kThreads - 1) / kThreads;   // output values per thread
+  constexpr int NWAVE = NT / 64;
+  constexpr int UPT = (M2 + NT - 1) / NT;       // combine units per thread
+  constexpr int VPT = (2 * M2 + NT - 1) / NT;   // output values per thread
   extern __shared__ __align__(16) unsigned char smem[];
 
   const int M1 = a.M1;
@@ -408,7 +415,7 @@ __global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs 
   int* tab = (int*)(sdot + a.umax);                      // tab_max
 
   const int nrows = (k1 == 0 || 2 * k1 == M1) ? 1 : 2;
-  const int rows[2] = {k1, M1 - k1};
+  auto row_of = [&](int rr) { return rr ? M1 - k1 : k1; };   // the two rows (no indexed array)
   const int Tp = sd.Tp;
 
   // everything this work item reads from HBM is requested up front, in the
@@ -416,18 +423,18 @@ __global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs 
   const cplx<T>* Z1 = (const cplx<T>*)sd.Z1;
   const int nload = u * nrows * M2;
 #pragma unroll 8
-  for (int idx = tid; idx < nload; idx += kThreads) {
+  for (int idx = tid; idx < nload; idx += NT) {
     int cr = idx / M2, k2 = idx - cr * M2;
     int c = cr / nrows, rr = cr - c * nrows;
-    X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)c * M + (int64_t)rows[rr] * M2 + k2));
+    X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)c * M + (int64_t)row_of(rr) * M2 + k2));
   }
-  if (TW_LDS) load_table<T, M2, kThreads>(twl, a.twP2);
+  if (TW_LDS) load_table<T, M2, NT>(twl, a.twP2);
   const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
   const int64_t lmask = (int64_t(1) << a.b) - 1;
   cplx<T> wkh[UPT], wkl[UPT];   // w_L^k of this thread's combine units (two table halves)
 #pragma unroll
   for (int i = 0; i < UPT; ++i) {
-    int unit = tid + i * kThreads;
+    int unit = tid + i * NT;
     int64_t e = k1 + (int64_t)M1 * unit;
     wkh[i] = unit < nunits ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
     wkl[i] = unit < nunits ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
@@ -435,25 +442,25 @@ __global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs 
   cplx<T> wvh[VPT], wvl[VPT];   // w_M^(j2 row) of this thread's outputs (conjugated at use)
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
-    int idx = tid + i * kThreads;
+    int idx = tid + i * NT;
     int rr = idx / M2, j2 = idx - rr * M2;
-    int64_t e = (2 * (int64_t)j2 * rows[rr < 2 ? rr : 0]) & (a.L - 1);
+    int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) & (a.L - 1);
     wvh[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
     wvl[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
   }
-  for (int i = tid; i < sd.ntab; i += kThreads) tab[i] = ldg(sd.tab + i);
-  for (int i = tid; i < Tp + sd.Tq; i += kThreads) coef[i] = ldg(sd.coef + i);
+  for (int i = tid; i < sd.ntab; i += NT) tab[i] = ldg(sd.tab + i);
+  for (int i = tid; i < Tp + sd.Tq; i += NT) coef[i] = ldg(sd.coef + i);
   if (k1 == 0) {   // partial dots of the column pass -> per-wave sums
     const int ngroups = M2 / a.g;
     for (int c = 0; c < u; ++c) {
       double sacc = 0.0;
-      for (int q = tid; q < ngroups; q += kThreads) sacc += ldg(sd.dots + ((size_t)c * ngroups + q));
+      for (int q = tid; q < ngroups; q += NT) sacc += ldg(sd.dots + ((size_t)c * ngroups + q));
       sacc = wave_sum(sacc);
       if (lane == 0) red[wave * a.umax + c] = sacc;
     }
   }
   lds_barrier();
-  fft_batch<T, M2, -1, NB, STR, kThreads, StageRadix<T>::value>(X, u * nrows, tw);
+  fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, u * nrows, tw);
 
   // bins k = k1 + M1*iA and M - k, spectra of the real inputs, their weighted
   // products, and the even/odd packing of the real inverse
@@ -461,7 +468,7 @@ __global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs 
   const int* pids = tab + sd.o_pids;
 #pragma unroll
   for (int i = 0; i < UPT; ++i) {
-    const int unit = tid + i * kThreads;
+    const int unit = tid + i * NT;
     if (unit >= nunits) continue;
     const int iA = unit;
     int iB, rB;
@@ -509,15 +516,15 @@ __global__ __launch_bounds__(kThreads, LEAN ? 5 : 1) void row_kernel(LaunchArgs 
     }
   }
   lds_barrier();
-  fft_batch<T, M2, +1, NB, STR, kThreads, StageRadix<T>::value>(X, nrows, tw);
+  fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T>::value>(X, nrows, tw);
 
   cplx<T>* V = (cplx<T>*)sd.V;
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
-    int idx = tid + i * kThreads;
+    int idx = tid + i * NT;
     if (idx < nrows * M2) {
       int rr = idx / M2, j2 = idx - rr * M2;
-      stg(V + ((int64_t)rows[rr] * M2 + j2), cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i])));
+      stg(V + ((int64_t)row_of(rr) * M2 + j2), cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i])));
     }
   }
 
@@ -651,7 +658,7 @@ static hipError_t launch_col_p(const LaunchArgs& a, hipStream_t s) {
 size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max) {
   size_t cs = prec == 1 ? 8 : 16;
   return (size_t)(M2 <= 512 ? M2 : 0) * cs + (size_t)umax * 2 * lds_len(M2) * cs + (size_t)umax * cs +
-         (size_t)coef_max * 8 + (size_t)(kThreads / 64 + 1) * umax * 8 + (size_t)tab_max * 4 + 16;
+         (size_t)coef_max * 8 + (size_t)(2 * kThreads / 64 + 1) * umax * 8 + (size_t)tab_max * 4 + 16;
 }
 
 int col_batch(int prec, int M1, int u, int nworkgroups) {
@@ -683,9 +690,9 @@ static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s, size_t smem) 
   }
   dim3 grid(a.nslots * (a.M1 / 2 + 1));
   if (lean)
-    hipLaunchKernelGGL((row_kernel<T, M2, kHasLean>), grid, dim3(kThreads), smem, s, a);
+    hipLaunchKernelGGL((row_kernel<T, M2, kHasLean>), grid, dim3(RowThreads<M2, kHasLean>::value), smem, s, a);
   else
-    hipLaunchKernelGGL((row_kernel<T, M2, false>), grid, dim3(kThreads), smem, s, a);
+    hipLaunchKernelGGL((row_kernel<T, M2, false>), grid, dim3(RowThreads<M2, false>::value), smem, s, a);
   return hipGetLastError();
 }
 

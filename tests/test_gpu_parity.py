@@ -196,6 +196,9 @@ def test_solve_c2_short_vs_oracle(prec):
 
 
 def test_batch_equals_single_bitwise():
+    """A batch slot computes what the state computes alone when both launches
+    use the same column group (here both narrow it to one column: 2 and 6
+    column groups are fewer than the CUs)."""
     D, N = 4, 777
     k = synth.kernel_ballistic(D, N, 0.3)
     states = [synth.n0_random_dense(N, 50 + b, decay=0.01) for b in range(3)]

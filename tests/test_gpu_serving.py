@@ -1,6 +1,9 @@
 """Serving engine on the GPU: requests of uneven N, D, kernel and length run
-concurrently (continuous batching) and each result equals the same solve run
-alone through agg_solve; admission, rejection and ticket handling."""
+concurrently (continuous batching); each result equals, bit for bit, the same
+request served alone by the engine, and agrees with agg_solve of the request
+within the parity tolerance (agg_solve may narrow the column group of a small
+launch, which regroups the binary64 partial dot products); admission,
+rejection and ticket handling."""
 import sys
 import time
 
@@ -26,6 +29,18 @@ def alone(r, prec):
     plan.solve(n, r["dt"], r["t_end"])
     out = n.cpu().numpy()
     plan.close()
+    return out
+
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-10}
+
+
+def served_alone(r, prec):
+    eng = agg.Engine(0)
+    t = eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec)
+    rc, out, st = drain(eng, [t], [r["N"]])[t]
+    eng.close()
+    assert rc == agg.AGG_OK
     return out
 
 
@@ -59,10 +74,12 @@ def test_mixed_requests_equal_alone(prec):
         rc, out, st = res[t]
         assert rc == agg.AGG_OK
         ref = alone(r, prec)
+        solo = served_alone(r, prec)
         say(f"[serve] D={r['D']} N={r['N']} a={r['a']:.2f} steps={st.steps} "
-            f"maxdiff={np.max(np.abs(out - ref)):.3e}")
+            f"maxdiff vs agg_solve={np.max(np.abs(out - ref)):.3e}")
         assert st.steps == len(__import__("oracle").time_grid(r["dt"], r["t_end"]))
-        assert np.array_equal(out, ref)        # slot arithmetic is independent of neighbours
+        assert np.array_equal(out, solo)       # slot arithmetic is independent of neighbours
+        assert np.max(np.abs(out - ref)) <= TOL[prec] * np.max(np.abs(ref))
         assert st.t_submit <= st.t_admit <= st.t_finish
 
 
