@@ -87,6 +87,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// The same value in every lane, held in scalar registers: a pointer that is
+// uniform over the workgroup (a slot's table) read through the constant address
+// space compiles to scalar loads, which need no LDS or vector-memory round trip.
+template <class T> __device__ __forceinline__ const __attribute__((address_space(4))) T* uniform_ptr(const T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (const __attribute__((address_space(4))) T*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // Descriptor of one slot: from device memory, or built from the launch's base
 // descriptor and strides (no dependent load before the first data request).
 __device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
@@ -463,9 +474,12 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
   fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, u * nrows, tw);
 
   // bins k = k1 + M1*iA and M - k, spectra of the real inputs, their weighted
-  // products, and the even/odd packing of the real inverse
-  const int* poff = tab;
-  const int* pids = tab + sd.o_pids;
+  // products, and the even/odd packing of the real inverse; the gain-term
+  // tables are read with scalar loads (uniform over the workgroup)
+  const auto poff = uniform_ptr(sd.tab);
+  const auto pids = uniform_ptr(sd.tab + sd.o_pids);
+  const auto pcoef = uniform_ptr(sd.coef);
+  const int Tpu = uniform_int(Tp);
 #pragma unroll
   for (int i = 0; i < UPT; ++i) {
     const int unit = tid + i * NT;
@@ -478,33 +492,67 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
     const bool zero_bin = (k1 == 0 && iA == 0);
     const bool self = (rB == 0 && iB == iA);
     const cplx<T> wk = cmul(wkh[i], wkl[i]);
-    for (int c = 0; c < u; ++c) {
-      cplx<T>* pA = &X[(c * nrows) * STR + lds_pad(iA)];
-      cplx<T>* pB = &X[(c * nrows + rB) * STR + lds_pad(iB)];
-      cplx<T> ZA = *pA, ZB = *pB;
+    // spectrum of real input c at bins A and B from the packed half-length
+    // spectrum Z: X(A) = E + t and X(B) = conj(E - t), E = (Z_A + conj Z_B)/2,
+    // t = w_L^k * (-i)(Z_A - conj Z_B)/2; at the zero bin X(0) = Re+Im of Z_0
+    // and the Nyquist value X(M) = Re-Im
+    auto unpack = [&](int c, cplx<T>& xa, cplx<T>& xb) {
+      const cplx<T> ZA = X[(c * nrows) * STR + lds_pad(iA)];
+      const cplx<T> ZB = X[(c * nrows + rB) * STR + lds_pad(iB)];
       if (zero_bin) {
-        *pA = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
-        nyq[c] = cplx<T>{ZA.re - ZA.im, Real<T>::zero()};
+        xa = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
+        xb = cplx<T>{ZA.re - ZA.im, Real<T>::zero()};
       } else {
         cplx<T> zc = cconj(ZB);
         cplx<T> E = cplx<T>{half_of(ZA.re + zc.re), half_of(ZA.im + zc.im)};
         cplx<T> dd = csub(ZA, zc);
         cplx<T> O = cplx<T>{half_of(dd.im), half_of(-dd.re)};   // -i*(ZA - conj ZB)/2
         cplx<T> t = cmul(wk, O);
-        *pA = cadd(E, t);
-        if (!self) *pB = cconj(csub(E, t));
+        xa = cadd(E, t);
+        xb = self ? xa : cconj(csub(E, t));
       }
-    }
+    };
     cplx<T> YA = czero<T>(), YB = czero<T>();
-    for (int t = 0; t < Tp; ++t) {
-      cplx<T> PA = cplx<T>{Real<T>::from_d(coef[t]), Real<T>::zero()}, PB = PA;
-      for (int o = poff[t]; o < poff[t + 1]; ++o) {
-        int c = pids[o];
-        PA = cmul(PA, X[(c * nrows) * STR + lds_pad(iA)]);
-        PB = cmul(PB, zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)]);
+    if (!LEAN && u <= kRowRegCols) {
+      // few distinct columns: the unpacked spectra stay in registers and the
+      // products select them by the (uniform) column id
+      cplx<T> xa[kRowRegCols], xb[kRowRegCols];
+#pragma unroll
+      for (int c = 0; c < kRowRegCols; ++c)
+        if (c < u) unpack(c, xa[c], xb[c]);
+      for (int t = 0; t < Tpu; ++t) {
+        cplx<T> PA = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()}, PB = PA;
+        const int oe = poff[t + 1];
+        for (int o = poff[t]; o < oe; ++o) {
+          const int c = pids[o];
+          cplx<T> fa = xa[0], fb = xb[0];
+#pragma unroll
+          for (int q = 1; q < kRowRegCols; ++q)
+            if (c == q) { fa = xa[q]; fb = xb[q]; }
+          PA = cmul(PA, fa);
+          PB = cmul(PB, fb);
+        }
+        YA = cadd(YA, PA);
+        YB = cadd(YB, PB);
       }
-      YA = cadd(YA, PA);
-      YB = cadd(YB, PB);
+    } else {
+      for (int c = 0; c < u; ++c) {
+        cplx<T> xa, xb;
+        unpack(c, xa, xb);
+        X[(c * nrows) * STR + lds_pad(iA)] = xa;
+        if (zero_bin) nyq[c] = xb;
+        else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = xb;
+      }
+      for (int t = 0; t < Tpu; ++t) {
+        cplx<T> PA = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()}, PB = PA;
+        for (int o = poff[t]; o < poff[t + 1]; ++o) {
+          int c = pids[o];
+          PA = cmul(PA, X[(c * nrows) * STR + lds_pad(iA)]);
+          PB = cmul(PB, zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)]);
+        }
+        YA = cadd(YA, PA);
+        YB = cadd(YB, PB);
+      }
     }
     if (zero_bin) {
       X[0] = cplx<T>{YA.re + YB.re, YA.re - YB.re};
