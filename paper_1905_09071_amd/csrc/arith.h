@@ -33,46 +33,56 @@ __device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& 
   e = b - (s - a);
 }
 
-// Dekker's addition: the error terms of the two high parts are kept exactly and
-// the low parts are added once, so |result - (a+b)| <= ~2^-47 (|a| + |b|).
-// That absolute bound is what the normwise error of a transform, a product of
+// Dekker's addition without the final renormalisation: the error term of the
+// two high parts is kept exactly and the low parts are added once, so
+// |result - (a+b)| <= ~2^-46 (|a| + |b|).  The pair it returns is not
+// renormalised (|lo| may exceed half an ulp of hi by a small factor); every
+// value that leaves registers (LDS, global memory) goes through ff_norm, which
+// bounds the growth of lo to the few operations between two stores.  The
+// absolute bound is what the normwise error of a transform, a product of
 // spectra and an inverse transform depends on; relative accuracy under
-// cancellation (the IEEE-style double-TwoSum addition) is not needed here.
+// cancellation is not needed here.
 __device__ __forceinline__ ff operator+(ff a, ff b) {
 #pragma clang fp contract(off)
   float s, e;
   two_sum(a.hi, b.hi, s, e);
   e += a.lo + b.lo;
-  ff r;
-  fast_two_sum(s, e, r.hi, r.lo);
-  return r;
+  return ff{s, e};
 }
 __device__ __forceinline__ ff operator-(ff a) { return ff{-a.hi, -a.lo}; }
 __device__ __forceinline__ ff operator-(ff a, ff b) { return a + (-b); }
+// Exact product of the high parts (FMA TwoProd) plus the two cross terms; the
+// pair is left unrenormalised as for the sum.
 __device__ __forceinline__ ff operator*(ff a, ff b) {
 #pragma clang fp contract(off)
   float p = a.hi * b.hi;
   float e = __builtin_fmaf(a.hi, b.hi, -p);
   e = __builtin_fmaf(a.hi, b.lo, e);
   e = __builtin_fmaf(a.lo, b.hi, e);
+  return ff{p, e};
+}
+__device__ __forceinline__ ff ff_norm(ff a) {
   ff r;
-  fast_two_sum(p, e, r.hi, r.lo);
+  fast_two_sum(a.hi, a.lo, r.hi, r.lo);
   return r;
 }
 
 // ---- conversions -----------------------------------------------------------
 template <class T> struct Real;
 template <> struct Real<double> {
+  static __device__ __forceinline__ double norm(double x) { return x; }
   static __device__ __forceinline__ double from_d(double x) { return x; }
   static __device__ __forceinline__ double to_d(double x) { return x; }
   static __device__ __forceinline__ double zero() { return 0.0; }
 };
 template <> struct Real<float> {
+  static __device__ __forceinline__ float norm(float x) { return x; }
   static __device__ __forceinline__ float from_d(double x) { return (float)x; }
   static __device__ __forceinline__ double to_d(float x) { return (double)x; }
   static __device__ __forceinline__ float zero() { return 0.0f; }
 };
 template <> struct Real<ff> {
+  static __device__ __forceinline__ ff norm(ff x) { return ff_norm(x); }
   static __device__ __forceinline__ ff from_d(double x) {
     float h = (float)x;
     return ff{h, (float)(x - (double)h)};
@@ -106,6 +116,11 @@ template <class T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {
 // multiply by +i and by -i
 template <class T> __device__ __forceinline__ cplx<T> cmul_i(cplx<T> a) { return cplx<T>{-a.im, a.re}; }
 template <class T> __device__ __forceinline__ cplx<T> cmul_negi(cplx<T> a) { return cplx<T>{a.im, -a.re}; }
+
+// renormalised copy (float-float) for storing; identity otherwise
+template <class T> __device__ __forceinline__ cplx<T> cnorm(cplx<T> a) {
+  return cplx<T>{Real<T>::norm(a.re), Real<T>::norm(a.im)};
+}
 
 template <class T> __device__ __forceinline__ cplx<T> czero() {
   return cplx<T>{Real<T>::zero(), Real<T>::zero()};

@@ -121,7 +121,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int nfft, const cplx<T>*
       dftR<T, R, DIR>(v[kk]);
       int base = (b / NS) * NS * R + j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[f * STR + lds_pad(base + r * NS)] = v[kk][r];
+      for (int r = 0; r < R; ++r) buf[f * STR + lds_pad(base + r * NS)] = cnorm(v[kk][r]);
     }
   }
   lds_barrier();

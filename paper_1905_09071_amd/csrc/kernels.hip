@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
         if (idx < nitems) {
           int k1 = idx >> lgg, jl = idx & (g - 1);
           stg(Z1 + ((size_t)(cb + q) * M + (int64_t)k1 * M2 + j2_0 + jl),
-              cmul(buf[(q * g + jl) * STR + lds_pad(k1)], wst[it]));
+              cnorm(cmul(buf[(q * g + jl) * STR + lds_pad(k1)], wst[it])));
         }
       }
     }
@@ -539,9 +539,9 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
       for (int c = 0; c < u; ++c) {
         cplx<T> xa, xb;
         unpack(c, xa, xb);
-        X[(c * nrows) * STR + lds_pad(iA)] = xa;
-        if (zero_bin) nyq[c] = xb;
-        else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = xb;
+        X[(c * nrows) * STR + lds_pad(iA)] = cnorm(xa);
+        if (zero_bin) nyq[c] = cnorm(xb);
+        else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
       }
       for (int t = 0; t < Tpu; ++t) {
         cplx<T> PA = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()}, PB = PA;
@@ -555,12 +555,12 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
       }
     }
     if (zero_bin) {
-      X[0] = cplx<T>{YA.re + YB.re, YA.re - YB.re};
+      X[0] = cnorm(cplx<T>{YA.re + YB.re, YA.re - YB.re});
     } else {
       cplx<T> F = cadd(YA, cconj(YB));
       cplx<T> Gd = csub(YA, cconj(YB));
-      X[lds_pad(iA)] = cadd(F, cmul_i(cmulc(Gd, wk)));
-      if (!self) X[rB * STR + lds_pad(iB)] = cadd(cconj(F), cmul_i(cmul(wk, cconj(Gd))));
+      X[lds_pad(iA)] = cnorm(cadd(F, cmul_i(cmulc(Gd, wk))));
+      if (!self) X[rB * STR + lds_pad(iB)] = cnorm(cadd(cconj(F), cmul_i(cmul(wk, cconj(Gd)))));
     }
   }
   lds_barrier();
@@ -572,7 +572,7 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
     int idx = tid + i * NT;
     if (idx < nrows * M2) {
       int rr = idx / M2, j2 = idx - rr * M2;
-      stg(V + ((int64_t)row_of(rr) * M2 + j2), cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i])));
+      stg(V + ((int64_t)row_of(rr) * M2 + j2), cnorm(cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i]))));
     }
   }
 
