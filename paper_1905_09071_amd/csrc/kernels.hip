@@ -98,6 +98,19 @@ template <class T> __device__ __forceinline__ const __attribute__((address_space
 }
 __device__ __forceinline__ int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// The value held by the neighbouring lane (lane ^ 1), word by word.
+template <class T> __device__ __forceinline__ cplx<T> lane_swap1(cplx<T> v) {
+  static_assert(sizeof(cplx<T>) % 4 == 0, "whole 32-bit words");
+  constexpr int W = sizeof(cplx<T>) / 4;
+  int w[W];
+  __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = __shfl_xor(w[i], 1, 64);
+  cplx<T> r;
+  __builtin_memcpy(&r, w, sizeof(r));
+  return r;
+}
+
 // Descriptor of one slot: from device memory, or built from the launch's base
 // descriptor and strides (no dependent load before the first data request).
 __device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
@@ -400,6 +413,8 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
   constexpr int STR = lds_len(M2);
   constexpr int NWAVE = NT / 64;
   constexpr int UPT = (M2 + NT - 1) / NT;       // combine units per thread
+  constexpr int HPT = (2 * M2 + NT - 1) / NT;   // combine half-units per thread (two lanes per unit)
+  constexpr int CPT = UPT > HPT ? UPT : HPT;
   constexpr int VPT = (2 * M2 + NT - 1) / NT;   // output values per thread
   extern __shared__ __align__(16) unsigned char smem[];
 
@@ -442,10 +457,13 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
   if (TW_LDS) load_table<T, M2, NT>(twl, a.twP2);
   const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
   const int64_t lmask = (int64_t(1) << a.b) - 1;
-  cplx<T> wkh[UPT], wkl[UPT];   // w_L^k of this thread's combine units (two table halves)
+  // combine mapping: with few distinct columns (non-lean variant) two adjacent
+  // lanes share a bin pair, one per bin; otherwise one thread per bin pair
+  const bool split = !LEAN && u <= kRowRegCols;
+  cplx<T> wkh[CPT], wkl[CPT];   // w_L^k of this thread's combine units (two table halves)
 #pragma unroll
-  for (int i = 0; i < UPT; ++i) {
-    int unit = tid + i * NT;
+  for (int i = 0; i < CPT; ++i) {
+    int unit = split ? (tid + i * NT) >> 1 : tid + i * NT;
     int64_t e = k1 + (int64_t)M1 * unit;
     wkh[i] = unit < nunits ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
     wkl[i] = unit < nunits ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
@@ -480,69 +498,112 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
   const auto pids = uniform_ptr(sd.tab + sd.o_pids);
   const auto pcoef = uniform_ptr(sd.coef);
   const int Tpu = uniform_int(Tp);
+  // bin pair of a unit: A = iA in row 0, B = its mirror (row rB)
+  auto pair_of = [&](int unit, int& iB, int& rB) {
+    if (k1 == 0) { iB = (M2 - unit) & (M2 - 1); rB = 0; }
+    else if (nrows == 1) { iB = M2 - 1 - unit; rB = 0; }
+    else { iB = M2 - 1 - unit; rB = 1; }
+  };
+  // spectrum of real input c at bins A and B from the packed half-length
+  // spectrum Z: X(A) = E + t and X(B) = conj(E - t), E = (Z_A + conj Z_B)/2,
+  // t = w_L^k * (-i)(Z_A - conj Z_B)/2; at the zero bin X(0) = Re+Im of Z_0
+  // and the Nyquist value X(M) = Re-Im
+  auto unpack = [&](int c, int iA, int iB, int rB, bool zero_bin, bool self, cplx<T> wk, cplx<T>& xa,
+                    cplx<T>& xb) {
+    const cplx<T> ZA = X[(c * nrows) * STR + lds_pad(iA)];
+    const cplx<T> ZB = X[(c * nrows + rB) * STR + lds_pad(iB)];
+    if (zero_bin) {
+      xa = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
+      xb = cplx<T>{ZA.re - ZA.im, Real<T>::zero()};
+    } else {
+      cplx<T> zc = cconj(ZB);
+      cplx<T> E = cplx<T>{half_of(ZA.re + zc.re), half_of(ZA.im + zc.im)};
+      cplx<T> dd = csub(ZA, zc);
+      cplx<T> O = cplx<T>{half_of(dd.im), half_of(-dd.re)};   // -i*(ZA - conj ZB)/2
+      cplx<T> t = cmul(wk, O);
+      xa = cadd(E, t);
+      xb = self ? xa : cconj(csub(E, t));
+    }
+  };
+  // even/odd packing of the real inverse from the combined spectrum at A and B
+  auto pack_a = [&](cplx<T> YA, cplx<T> YB, cplx<T> wk) {
+    return cadd(cadd(YA, cconj(YB)), cmul_i(cmulc(csub(YA, cconj(YB)), wk)));
+  };
+  auto pack_b = [&](cplx<T> YA, cplx<T> YB, cplx<T> wk) {
+    return cadd(cconj(cadd(YA, cconj(YB))), cmul_i(cmul(wk, cconj(csub(YA, cconj(YB))))));
+  };
+  if (split) {
+    // few distinct columns: each lane keeps its bin's unpacked spectra in
+    // registers and forms the products for that bin; the partner lane's sum
+    // arrives by a lane exchange.  Both lanes read a pair's inputs with the same
+    // LDS instructions before either writes, and the lanes of a wave run in
+    // lockstep, so no barrier is needed.
 #pragma unroll
-  for (int i = 0; i < UPT; ++i) {
-    const int unit = tid + i * NT;
-    if (unit >= nunits) continue;
-    const int iA = unit;
-    int iB, rB;
-    if (k1 == 0) { iB = (M2 - iA) & (M2 - 1); rB = 0; }
-    else if (nrows == 1) { iB = M2 - 1 - iA; rB = 0; }
-    else { iB = M2 - 1 - iA; rB = 1; }
-    const bool zero_bin = (k1 == 0 && iA == 0);
-    const bool self = (rB == 0 && iB == iA);
-    const cplx<T> wk = cmul(wkh[i], wkl[i]);
-    // spectrum of real input c at bins A and B from the packed half-length
-    // spectrum Z: X(A) = E + t and X(B) = conj(E - t), E = (Z_A + conj Z_B)/2,
-    // t = w_L^k * (-i)(Z_A - conj Z_B)/2; at the zero bin X(0) = Re+Im of Z_0
-    // and the Nyquist value X(M) = Re-Im
-    auto unpack = [&](int c, cplx<T>& xa, cplx<T>& xb) {
-      const cplx<T> ZA = X[(c * nrows) * STR + lds_pad(iA)];
-      const cplx<T> ZB = X[(c * nrows + rB) * STR + lds_pad(iB)];
-      if (zero_bin) {
-        xa = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
-        xb = cplx<T>{ZA.re - ZA.im, Real<T>::zero()};
-      } else {
-        cplx<T> zc = cconj(ZB);
-        cplx<T> E = cplx<T>{half_of(ZA.re + zc.re), half_of(ZA.im + zc.im)};
-        cplx<T> dd = csub(ZA, zc);
-        cplx<T> O = cplx<T>{half_of(dd.im), half_of(-dd.re)};   // -i*(ZA - conj ZB)/2
-        cplx<T> t = cmul(wk, O);
-        xa = cadd(E, t);
-        xb = self ? xa : cconj(csub(E, t));
+    for (int i = 0; i < HPT; ++i) {
+      const int h = tid + i * NT;
+      const int unit = h >> 1, side = h & 1;
+      const bool valid = unit < nunits;
+      int iB, rB;
+      pair_of(unit, iB, rB);
+      const int iA = unit;
+      const bool zero_bin = (k1 == 0 && iA == 0);
+      const bool self = (rB == 0 && iB == iA);
+      const cplx<T> wk = cmul(wkh[i], wkl[i]);
+      cplx<T> x[kRowRegCols];
+#pragma unroll
+      for (int c = 0; c < kRowRegCols; ++c) {
+        x[c] = czero<T>();
+        if (valid && c < u) {
+          cplx<T> xa, xb;
+          unpack(c, iA, iB, rB, zero_bin, self, wk, xa, xb);
+          x[c] = side ? xb : xa;
+        }
       }
-    };
-    cplx<T> YA = czero<T>(), YB = czero<T>();
-    if (!LEAN && u <= kRowRegCols) {
-      // few distinct columns: the unpacked spectra stay in registers and the
-      // products select them by the (uniform) column id
-      cplx<T> xa[kRowRegCols], xb[kRowRegCols];
-#pragma unroll
-      for (int c = 0; c < kRowRegCols; ++c)
-        if (c < u) unpack(c, xa[c], xb[c]);
+      cplx<T> Y = czero<T>();
       for (int t = 0; t < Tpu; ++t) {
-        cplx<T> PA = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()}, PB = PA;
+        cplx<T> P = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()};
         const int oe = poff[t + 1];
         for (int o = poff[t]; o < oe; ++o) {
           const int c = pids[o];
-          cplx<T> fa = xa[0], fb = xb[0];
+          cplx<T> f = x[0];
 #pragma unroll
           for (int q = 1; q < kRowRegCols; ++q)
-            if (c == q) { fa = xa[q]; fb = xb[q]; }
-          PA = cmul(PA, fa);
-          PB = cmul(PB, fb);
+            if (c == q) f = x[q];
+          P = cmul(P, f);
         }
-        YA = cadd(YA, PA);
-        YB = cadd(YB, PB);
+        Y = cadd(Y, P);
       }
-    } else {
+      const cplx<T> Yp = lane_swap1(Y);
+      if (valid) {
+        const cplx<T> YA = side ? Yp : Y, YB = side ? Y : Yp;
+        if (zero_bin) {
+          if (side == 0) X[0] = cnorm(cplx<T>{YA.re + YB.re, YA.re - YB.re});
+        } else if (side == 0) {
+          X[lds_pad(iA)] = cnorm(pack_a(YA, YB, wk));
+        } else if (!self) {
+          X[rB * STR + lds_pad(iB)] = cnorm(pack_b(YA, YB, wk));
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int unit = tid + i * NT;
+      if (unit >= nunits) continue;
+      int iB, rB;
+      pair_of(unit, iB, rB);
+      const int iA = unit;
+      const bool zero_bin = (k1 == 0 && iA == 0);
+      const bool self = (rB == 0 && iB == iA);
+      const cplx<T> wk = cmul(wkh[i], wkl[i]);
       for (int c = 0; c < u; ++c) {
         cplx<T> xa, xb;
-        unpack(c, xa, xb);
+        unpack(c, iA, iB, rB, zero_bin, self, wk, xa, xb);
         X[(c * nrows) * STR + lds_pad(iA)] = cnorm(xa);
         if (zero_bin) nyq[c] = cnorm(xb);
         else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
       }
+      cplx<T> YA = czero<T>(), YB = czero<T>();
       for (int t = 0; t < Tpu; ++t) {
         cplx<T> PA = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()}, PB = PA;
         for (int o = poff[t]; o < poff[t + 1]; ++o) {
@@ -553,14 +614,12 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
         YA = cadd(YA, PA);
         YB = cadd(YB, PB);
       }
-    }
-    if (zero_bin) {
-      X[0] = cnorm(cplx<T>{YA.re + YB.re, YA.re - YB.re});
-    } else {
-      cplx<T> F = cadd(YA, cconj(YB));
-      cplx<T> Gd = csub(YA, cconj(YB));
-      X[lds_pad(iA)] = cnorm(cadd(F, cmul_i(cmulc(Gd, wk))));
-      if (!self) X[rB * STR + lds_pad(iB)] = cnorm(cadd(cconj(F), cmul_i(cmul(wk, cconj(Gd)))));
+      if (zero_bin) {
+        X[0] = cnorm(cplx<T>{YA.re + YB.re, YA.re - YB.re});
+      } else {
+        X[lds_pad(iA)] = cnorm(pack_a(YA, YB, wk));
+        if (!self) X[rB * STR + lds_pad(iB)] = cnorm(pack_b(YA, YB, wk));
+      }
     }
   }
   lds_barrier();
