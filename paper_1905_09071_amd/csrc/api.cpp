@@ -95,12 +95,21 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 SharedImage make_shared_image(const PlanTables& T) {
   SharedImage im;
   const int64_t N = T.N;
-  std::vector<int> p_off{0}, p_ids, q_off{0}, q_ids, q_km;
+  std::vector<int> p_off{0}, p_ids, q_off{0}, q_ids, q_km, p_from;
   std::vector<double> coef;
   for (size_t t = 0; t < T.p_ids.size(); ++t) {
     for (int id : T.p_ids[t]) p_ids.push_back(id);
     p_off.push_back((int)p_ids.size());
     coef.push_back((double)T.p_mult[t] / factorial((int)T.p_ids[t].size()));
+    // a term whose ids start with all of the previous term's ids continues
+    // that term's running product (same-order multiplications, fewer of them)
+    int from = p_off[t];
+    if (t > 0) {
+      const std::vector<int>& a = T.p_ids[t - 1];
+      const std::vector<int>& b = T.p_ids[t];
+      if (a.size() < b.size() && std::equal(a.begin(), a.end(), b.begin())) from += (int)a.size();
+    }
+    p_from.push_back(from);
   }
   for (size_t t = 0; t < T.q_ids.size(); ++t) {
     for (int id : T.q_ids[t]) q_ids.push_back(id);
@@ -119,6 +128,7 @@ SharedImage make_shared_image(const PlanTables& T) {
   im.o_qoff = put(q_off);
   im.o_qids = put(q_ids);
   im.o_qkm = put(q_km);
+  im.o_pfrom = put(p_from);
   im.ntab = (int)blob.size();
   im.Tp = (int)T.p_ids.size();
   im.Tq = (int)T.q_ids.size();
@@ -159,7 +169,7 @@ void bind_shared(const SharedImage& im, void* dev, SharedTables* st) {
   st->twLlo = b + im.o_twlo;
   st->twLhi = b + im.o_twhi;
   st->Tp = im.Tp; st->Tq = im.Tq; st->ntab = im.ntab;
-  st->o_pids = im.o_pids; st->o_qoff = im.o_qoff; st->o_qids = im.o_qids; st->o_qkm = im.o_qkm;
+  st->o_pids = im.o_pids; st->o_qoff = im.o_qoff; st->o_qids = im.o_qids; st->o_qkm = im.o_qkm; st->o_pfrom = im.o_pfrom;
 }
 
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st) {
@@ -204,7 +214,7 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   if ((rc = arena.alloc((size_t)s.ntil * batch, (void**)&sd->ntil))) return rc;
   sd->cols = st.cols;
   sd->tab = st.tabs; sd->coef = st.coef; sd->ntab = st.ntab;
-  sd->o_pids = st.o_pids; sd->o_qoff = st.o_qoff; sd->o_qids = st.o_qids; sd->o_qkm = st.o_qkm;
+  sd->o_pids = st.o_pids; sd->o_qoff = st.o_qoff; sd->o_qids = st.o_qids; sd->o_qkm = st.o_qkm; sd->o_pfrom = st.o_pfrom;
   sd->N = (int)T.N; sd->u = T.u; sd->Tp = st.Tp; sd->Tq = st.Tq;
   sd->mode = CM_NONE; sd->row_on = 0; sd->dt = 0.0;
   if (stride) *stride = s;

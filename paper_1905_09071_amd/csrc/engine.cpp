@@ -217,7 +217,7 @@ bool Engine::setup_device(Request& r) {
   s.tab = r.st.tabs;
   s.coef = r.st.coef;
   s.ntab = r.st.ntab;
-  s.o_pids = r.st.o_pids; s.o_qoff = r.st.o_qoff; s.o_qids = r.st.o_qids; s.o_qkm = r.st.o_qkm;
+  s.o_pids = r.st.o_pids; s.o_qoff = r.st.o_qoff; s.o_qids = r.st.o_qids; s.o_qkm = r.st.o_qkm; s.o_pfrom = r.st.o_pfrom;
   s.N = (int)r.tab.N; s.u = r.tab.u; s.Tp = r.st.Tp; s.Tq = r.st.Tq;
   if (!spare_events.empty()) {
     r.done_ev = spare_events.back();

@@ -43,11 +43,12 @@ struct SlotDesc {
   void* V;                // M stored complex values
   double* dots;           // u*ngroups partial dot products (column kernel -> row kernel)
   double* G;              // u loss-term weights of the current evaluation
-  // term tables, one int blob: p_off[Tp+1] | p_ids | q_off[Tq+1] | q_ids | q_kmode[Tq]
+  // term tables, one int blob: p_off[Tp+1] | p_ids | q_off[Tq+1] | q_ids | q_kmode[Tq] | p_from[Tp]
+  // (p_from[t] > p_off[t]: gain term t extends term t-1, whose ids are its prefix)
   // (offsets below), and one binary64 blob: p_coef[Tp] (mult/d!) | q_coef[Tq] (mult/(d-1)!)
   const int* tab;
   const double* coef;
-  int ntab, o_pids, o_qoff, o_qids, o_qkm;
+  int ntab, o_pids, o_qoff, o_qids, o_qkm, o_pfrom;
   int N, u, Tp, Tq;
   int mode;               // per-slot column mode (when the launch mode is < 0)
   int row_on;             // per-slot row pass switch (when the launch mode is < 0)

@@ -497,6 +497,7 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
   const auto poff = uniform_ptr(sd.tab);
   const auto pids = uniform_ptr(sd.tab + sd.o_pids);
   const auto pcoef = uniform_ptr(sd.coef);
+  const auto pfrom = uniform_ptr(sd.tab + sd.o_pfrom);
   const int Tpu = uniform_int(Tp);
   // bin pair of a unit: A = iA in row 0, B = its mirror (row rB)
   auto pair_of = [&](int unit, int& iB, int& rB) {
@@ -559,19 +560,23 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
           x[c] = side ? xb : xa;
         }
       }
-      cplx<T> Y = czero<T>();
+      // running product over the ids of each term (continued from the
+      // previous term when that one is its prefix), times the coefficient
+      cplx<T> Y = czero<T>(), P = czero<T>();
       for (int t = 0; t < Tpu; ++t) {
-        cplx<T> P = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()};
         const int oe = poff[t + 1];
-        for (int o = poff[t]; o < oe; ++o) {
+        int o = pfrom[t];
+        bool fresh = o == poff[t];
+        for (; o < oe; ++o) {
           const int c = pids[o];
           cplx<T> f = x[0];
 #pragma unroll
           for (int q = 1; q < kRowRegCols; ++q)
             if (c == q) f = x[q];
-          P = cmul(P, f);
+          P = fresh ? f : cmul(P, f);
+          fresh = false;
         }
-        Y = cadd(Y, P);
+        Y = cadd(Y, cscale(P, Real<T>::from_d(pcoef[t])));
       }
       const cplx<T> Yp = lane_swap1(Y);
       if (valid) {
@@ -603,16 +608,22 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void r
         if (zero_bin) nyq[c] = cnorm(xb);
         else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
       }
-      cplx<T> YA = czero<T>(), YB = czero<T>();
+      cplx<T> YA = czero<T>(), YB = czero<T>(), PA = czero<T>(), PB = czero<T>();
       for (int t = 0; t < Tpu; ++t) {
-        cplx<T> PA = cplx<T>{Real<T>::from_d(pcoef[t]), Real<T>::zero()}, PB = PA;
-        for (int o = poff[t]; o < poff[t + 1]; ++o) {
+        const int oe = poff[t + 1];
+        int o = pfrom[t];
+        bool fresh = o == poff[t];
+        for (; o < oe; ++o) {
           int c = pids[o];
-          PA = cmul(PA, X[(c * nrows) * STR + lds_pad(iA)]);
-          PB = cmul(PB, zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)]);
+          const cplx<T> fa = X[(c * nrows) * STR + lds_pad(iA)];
+          const cplx<T> fb = zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)];
+          PA = fresh ? fa : cmul(PA, fa);
+          PB = fresh ? fb : cmul(PB, fb);
+          fresh = false;
         }
-        YA = cadd(YA, PA);
-        YB = cadd(YB, PB);
+        const T cf = Real<T>::from_d(pcoef[t]);
+        YA = cadd(YA, cscale(PA, cf));
+        YB = cadd(YB, cscale(PB, cf));
       }
       if (zero_bin) {
         X[0] = cnorm(cplx<T>{YA.re + YB.re, YA.re - YB.re});
