@@ -141,7 +141,7 @@ def cpu_baseline(c, budget_s: float):
         oracle.rhs_fft(c["D"], c["N"], c["kernel"], n)
         evals += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or evals >= 40:
+        if el >= budget_s or evals >= 400:
             break
     _ = np
     return evals / el, evals, el
