@@ -144,14 +144,18 @@ SharedImage make_shared_image(const PlanTables& T) {
                                       twiddle_bytes(T.prec, wlo), twiddle_bytes(T.prec, whi)};
 
   size_t off = 0;
-  im.o_cols = off; off = align256(off + (size_t)T.u * N * 8);
+  const int64_t CL = colorder_len(N, T.M2);
+  im.o_cols = off; off = align256(off + (size_t)T.u * CL * 8);
   im.o_tabs = off; off = align256(off + std::max<size_t>(blob.size(), 1) * 4);
   im.o_coef = off; off = align256(off + std::max<size_t>(coef.size(), 1) * 8);
   size_t* two[4] = {&im.o_tw1, &im.o_tw2, &im.o_twlo, &im.o_twhi};
   for (int i = 0; i < 4; ++i) { *two[i] = off; off = align256(off + tw[i].size()); }
   im.bytes.assign(off, 0);
-  for (int c = 0; c < T.u; ++c)
-    std::memcpy(&im.bytes[im.o_cols + (size_t)c * N * 8], T.ucols[c].data(), sizeof(double) * N);
+  // factor columns in the column pass's column order (size 0 and sizes past N stay 0)
+  for (int c = 0; c < T.u; ++c) {
+    double* dst = (double*)&im.bytes[im.o_cols + (size_t)c * CL * 8];
+    for (int64_t s = 1; s <= N; ++s) dst[colorder_index(s, N, T.M2)] = T.ucols[c][s - 1];
+  }
   if (!blob.empty()) std::memcpy(&im.bytes[im.o_tabs], blob.data(), blob.size() * 4);
   if (!coef.empty()) std::memcpy(&im.bytes[im.o_coef], coef.data(), coef.size() * 8);
   for (int i = 0; i < 4; ++i) std::memcpy(&im.bytes[*two[i]], tw[i].data(), tw[i].size());
@@ -189,7 +193,7 @@ size_t slot_bytes(const PlanTables& T) {
   size_t cs = complex_bytes(T.prec);
   size_t ngroups = T.M2;
   return (size_t)T.u * T.M * cs + (size_t)T.M * cs + (size_t)T.u * ngroups * 8 + (size_t)T.u * 8 +
-         2 * (size_t)T.N * 8;
+         2 * (size_t)colorder_len(T.N, T.M2) * 8;
 }
 
 // Buffers of `batch` slots sharing one kernel set, each kind carved from one
@@ -204,7 +208,7 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   s.V = (int64_t)((size_t)T.M * cs);
   s.dots = (int64_t)((size_t)T.u * ngroups * 8);
   s.G = (int64_t)((size_t)std::max(T.u, 1) * 8);
-  s.k1 = s.ntil = (int64_t)((size_t)T.N * 8);
+  s.k1 = s.ntil = (int64_t)((size_t)colorder_len(T.N, T.M2) * 8);   // column order
   std::memset(sd, 0, sizeof(*sd));
   if ((rc = arena.alloc((size_t)s.Z1 * batch, &sd->Z1))) return rc;
   if ((rc = arena.alloc((size_t)s.V * batch, &sd->V))) return rc;

@@ -98,10 +98,11 @@ struct ReqLayout {
 static ReqLayout request_layout(const PlanTables& T, size_t image_bytes) {
   ReqLayout l;
   size_t cs = complex_bytes(T.prec), ngroups = T.M2 / T.g, nb = (size_t)T.N * 8;
+  size_t cb = (size_t)colorder_len(T.N, T.M2) * 8;   // k1 and n~ in column order
   size_t off = align256(image_bytes);
   l.o_n = off; off = align256(off + nb);
-  l.o_k1 = off; off = align256(off + nb);
-  l.o_nt = off; off = align256(off + nb);
+  l.o_k1 = off; off = align256(off + cb);
+  l.o_nt = off; off = align256(off + cb);
   l.o_G = off; off = align256(off + (size_t)std::max(T.u, 1) * 8);
   l.o_dots = off; off = align256(off + (size_t)T.u * ngroups * 8);
   l.o_V = off; off = align256(off + (size_t)T.M * cs);

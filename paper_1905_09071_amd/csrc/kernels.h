@@ -90,6 +90,7 @@ constexpr int kColThreads = 512;         // threads of a column-pass workgroup
 constexpr int kColPrefetch = 4;          // factor columns held in registers by the column pass
 constexpr int kColLdsBudget = 120 * 1024; // LDS the column pass may use
 constexpr int kLeanWorkgroups = 512;     // column-pass workgroups from which a launch counts as saturating
+constexpr int kLeanMaxM1 = 512;          // largest column length with a lean column-pass variant
 constexpr int kRowRegCols = 4;          // row pass: distinct columns up to which unpacked spectra stay in registers
 constexpr int kSpreadWorkgroups = 256;   // column-pass workgroups a small launch is spread over (one per CU)
 

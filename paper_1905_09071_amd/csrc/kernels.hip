@@ -184,7 +184,6 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   const bool inv = mode_has_inverse(mode), fwd = mode_has_forward(mode);
   const bool stage2 = (mode == CM_H2 || mode == CM_H2_FWD);
   double* state = a.ext_state ? a.ext_state + (size_t)slot * N : sd.n_state;
-  const double* ev = stage2 ? sd.ntil : state;   // state at which f is taken
 
   // ---- one round of global requests, issued in the order they are needed
   // (completions are counted in issue order) ----
@@ -205,22 +204,29 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   double Gv[UPA];
 #pragma unroll
   for (int q = 0; q < UPA; ++q) Gv[q] = (inv && q < u) ? ldg(sd.G + q) : 0.0;
-  int64_t pos[IPT];          // size 2j of each item (2j+1 is the odd partner)
+  // sizes 2j, 2j+1 of each item; the vectors only this pass touches (k1, n~ and
+  // the factor columns) are stored in column order, item (j2, j1, e) at
+  // 2 (j2 J + j1) + e with J = N/(2 M2) + 1 rows, so a workgroup's accesses are
+  // contiguous; the caller's state keeps the size order
+  const int64_t Jr = N / (2 * (int64_t)M2) + 1;
+  const int64_t CSZ = 2 * (int64_t)M2 * Jr;
+  int64_t pos[IPT], cix[IPT];
   double pe[IPT][2], pn[IPT][2], pk[IPT][2], uc[UPA][IPT][2];
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     int idx = tid + it * NT;
     int j1 = idx >> lgg, jl = idx & (g - 1);
     pos[it] = idx < nitems ? 2 * (j2_0 + jl + (int64_t)M2 * j1) : N + 1;
+    cix[it] = idx < nitems ? 2 * ((int64_t)(j2_0 + jl) * Jr + j1) : 0;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      int64_t s = pos[it] + e;
+      int64_t s = pos[it] + e, ci = cix[it] + e;
       bool ok = s >= 1 && s <= N;
-      pe[it][e] = ok ? ldg(ev + (s - 1)) : 0.0;
+      pe[it][e] = ok ? (stage2 ? ldg(sd.ntil + ci) : ldg(state + (s - 1))) : 0.0;
       pn[it][e] = (!LEAN && ok && stage2) ? ldg(state + (s - 1)) : 0.0;
-      pk[it][e] = (!LEAN && ok && stage2) ? ldg(sd.k1 + (s - 1)) : 0.0;
+      pk[it][e] = (!LEAN && ok && stage2) ? ldg(sd.k1 + ci) : 0.0;
 #pragma unroll
-      for (int q = 0; q < UP; ++q) uc[q][it][e] = (ok && q < u) ? ldg(sd.cols + ((size_t)q * N + (s - 1))) : 0.0;
+      for (int q = 0; q < UP; ++q) uc[q][it][e] = (ok && q < u) ? ldg(sd.cols + ((size_t)q * CSZ + ci)) : 0.0;
     }
   }
   // four-step twiddles w_M^(j2 k1) (two table halves; multiplied when used)
@@ -269,13 +275,13 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     }
     for (int c = UP; c < u; ++c) {
       const double Gc = ldg(sd.G + c);
-      const double* col = sd.cols + (size_t)c * N;
+      const double* col = sd.cols + (size_t)c * CSZ;
 #pragma unroll
       for (int it = 0; it < IPT; ++it)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           int64_t s = pos[it] + e;
-          if (s >= 1 && s <= N) gk[it][e] += ldg(col + (s - 1)) * Gc;
+          if (s >= 1 && s <= N) gk[it][e] += ldg(col + (cix[it] + e)) * Gc;
         }
     }
 
@@ -302,12 +308,12 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
             } else if (mode == CM_RHS_ACC) {
               stg(out + (s - 1), ldg(out + (s - 1)) + f);
             } else if (mode == CM_H1) {
-              stg(sd.k1 + (s - 1), f);
+              stg(sd.k1 + (cix[it] + e), f);
               val = pe[it][e] + dt * f;
-              stg(sd.ntil + (s - 1), val);
+              stg(sd.ntil + (cix[it] + e), val);
             } else {
               const double nb = LEAN ? ldg(state + (s - 1)) : pn[it][e];
-              const double kb = LEAN ? ldg(sd.k1 + (s - 1)) : pk[it][e];
+              const double kb = LEAN ? ldg(sd.k1 + (cix[it] + e)) : pk[it][e];
               val = nb + 0.5 * dt * (kb + f);
               stg(state + (s - 1), val);
             }
@@ -353,7 +359,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
       }
     }
     for (int c = cb > UP ? cb : UP; c < cb + nc; ++c) {
-      const double* col = sd.cols + (size_t)c * N;
+      const double* col = sd.cols + (size_t)c * CSZ;
       double dsum = 0.0;
 #pragma unroll
       for (int it = 0; it < IPT; ++it) {
@@ -361,8 +367,8 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
         if (idx < nitems) {
           int j1 = idx >> lgg, jl = idx & (g - 1);
           int64_t s = pos[it];
-          double x0 = (s >= 1 && s <= N) ? ldg(col + (s - 1)) * s0[it] : 0.0;
-          double x1 = (s + 1 <= N) ? ldg(col + s) * s1[it] : 0.0;
+          double x0 = (s >= 1 && s <= N) ? ldg(col + cix[it]) * s0[it] : 0.0;
+          double x1 = (s + 1 <= N) ? ldg(col + (cix[it] + 1)) * s1[it] : 0.0;
           buf[((c - cb) * g + jl) * STR + lds_pad(j1)] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
           dsum += x0 + x1;
         }
@@ -409,7 +415,9 @@ template <class T, int M2, bool LEAN>
 __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void row_kernel(LaunchArgs a) {
   constexpr int NT = RowThreads<M2, LEAN>::value;
   constexpr bool TW_LDS = M2 <= 512;
-  constexpr int NB = (2048 / M2) > 0 ? 2048 / M2 : 1;
+  // transforms per register pass: 2048 values for 256 threads, twice that for
+  // 512 threads at the longest rows (so every thread holds a butterfly)
+  constexpr int NB = (M2 >= 1024 && NT > kThreads) ? 4096 / M2 : ((2048 / M2) > 0 ? 2048 / M2 : 1);
   constexpr int STR = lds_len(M2);
   constexpr int NWAVE = NT / 64;
   constexpr int UPT = (M2 + NT - 1) / NT;       // combine units per thread
@@ -752,7 +760,11 @@ static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
   constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
   size_t smem = ((size_t)M1 + (size_t)a.ub * GMAX * lds_len(M1)) * sizeof(cplx<T>);
   dim3 grid(a.nslots * (a.M2 / a.g));
-  if (a.lean) return launch_col_v<T, M1, true>(a, s, smem, grid);
+  // from M1 = 1024 the register cap of the lean variant (two workgroups per CU)
+  // spills the per-item state to scratch; those launches keep every register
+  if constexpr (M1 <= kLeanMaxM1) {
+    if (a.lean) return launch_col_v<T, M1, true>(a, s, smem, grid);
+  }
   return launch_col_v<T, M1, false>(a, s, smem, grid);
 }
 

@@ -42,6 +42,14 @@ void twiddle_at(int64_t P, int64_t e, double* re, double* im);
 // Time grid of a solve: number of steps and the size of the last one.
 void time_grid(double dt, double t_end, int64_t* nsteps, double* last_dt);
 
+// Length of a vector stored in the column pass's column order: size s = 2 j + e
+// with j = j2 + M2 j1 sits at 2 (j2 J + j1) + e, J = N/(2 M2) + 1 rows.
+inline int64_t colorder_len(int64_t N, int M2) { return 2 * (int64_t)M2 * (N / (2 * (int64_t)M2) + 1); }
+inline int64_t colorder_index(int64_t s, int64_t N, int M2) {
+  const int64_t J = N / (2 * (int64_t)M2) + 1, j = s >> 1;
+  return 2 * ((j % M2) * J + j / M2) + (s & 1);
+}
+
 // Bytes of one stored complex value of the spectral path for a precision.
 inline int complex_bytes(int prec) { return prec == AGG_FP32 ? 8 : 16; }
 
