@@ -10,6 +10,10 @@
 // computes exactly what it would compute alone: nothing in a slot's arithmetic
 // depends on its neighbours.  Requests that arrive while others run join at
 // the next tick; finished slots are copied out and their memory returned.
+// Buckets are independent within a tick, so with several buckets each one runs
+// on one of a few lane streams (forked from and joined back into the
+// scheduler's stream), letting small launches of different lengths share the
+// GPU instead of queueing behind each other.
 //
 // Memory: the engine owns one device region (its budget) and one pinned host
 // region, each carved by a first-fit allocator.  A request holds one
@@ -140,7 +144,10 @@ using BucketKey = std::tuple<int64_t, int, int, int, int>;   // L, M1, M2, g, pr
 
 struct Engine {
   agg_engine_config cfg{};
-  hipStream_t stream = nullptr;      // uploads, kernels and result copies
+  hipStream_t stream = nullptr;      // uploads, descriptors, result copies, single-bucket ticks
+  static constexpr int kLanes = 4;
+  hipStream_t lanes[kLanes] = {nullptr};   // bucket launches of multi-bucket ticks
+  hipEvent_t fork_ev = nullptr, join_ev[kLanes] = {nullptr};
   std::thread worker;
   std::mutex mu;                     // queue, done, known, stop
   std::condition_variable cv;
@@ -314,7 +321,12 @@ void Engine::tick() {
     base += L.cnt;
   }
   hipError_t e = hipMemcpyAsync(dd, hd, sizeof(SlotDesc) * base, hipMemcpyHostToDevice, stream);
+  const bool multi = launches.size() > 1;
+  const int nl = multi ? (int)std::min<size_t>(launches.size(), kLanes) : 0;
+  if (multi && e == hipSuccess) e = hipEventRecord(fork_ev, stream);
+  for (int l = 0; l < nl && e == hipSuccess; ++l) e = hipStreamWaitEvent(lanes[l], fork_ev, 0);
   for (size_t b = 0; b < launches.size() && e == hipSuccess; ++b) {
+    hipStream_t ls = multi ? lanes[b % kLanes] : stream;
     const Launch& L = launches[b];
     const PlanTables& T = L.first->tab;
     // every slot of a bucket has identical twiddle tables: take the first's
@@ -326,8 +338,12 @@ void Engine::tick() {
     a.lean = nwg >= kLeanWorkgroups ? 1 : 0;
     a.tab_max = L.tab_max;
     a.coef_max = L.coef_max;
-    e = launch_row(T.prec, a, stream);
-    if (e == hipSuccess) e = launch_col(T.prec, a, stream);
+    e = launch_row(T.prec, a, ls);
+    if (e == hipSuccess) e = launch_col(T.prec, a, ls);
+  }
+  for (int l = 0; l < nl && e == hipSuccess; ++l) {
+    e = hipEventRecord(join_ev[l], lanes[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, join_ev[l], 0);
   }
   if (e == hipSuccess) e = hipEventRecord(ring_ev[slot_ring], stream);
   ring_used[slot_ring] = true;
@@ -394,6 +410,7 @@ void Engine::run() {
     retire(idle_launches && !finishing.empty());
   }
   (void)hipStreamSynchronize(stream);
+  for (hipStream_t l : lanes) (void)hipStreamSynchronize(l);
   for (auto* v : {&running, &finishing})
     for (auto& rp : *v) release(*rp);
 }
@@ -416,6 +433,11 @@ static void engine_free(Engine& g) {
   g.spare_events.clear();
   if (g.dev_base) (void)hipFree(g.dev_base);
   if (g.host_base) (void)hipHostFree(g.host_base);
+  for (int l = 0; l < Engine::kLanes; ++l) {
+    if (g.lanes[l]) (void)hipStreamDestroy(g.lanes[l]);
+    if (g.join_ev[l]) (void)hipEventDestroy(g.join_ev[l]);
+  }
+  if (g.fork_ev) (void)hipEventDestroy(g.fork_ev);
   if (g.stream) (void)hipStreamDestroy(g.stream);
 }
 
@@ -442,6 +464,11 @@ agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out) {
   g.cap_slots = c.max_slots;
   e = hipSetDevice(c.device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking);
+  for (int l = 0; l < Engine::kLanes && e == hipSuccess; ++l) {
+    e = hipStreamCreateWithFlags(&g.lanes[l], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g.join_ev[l], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g.fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc((void**)&g.dev_base, (size_t)c.mem_budget);
   if (e == hipSuccess) e = hipHostMalloc((void**)&g.host_base, (size_t)host_bytes, hipHostMallocDefault);
   for (int i = 0; i < Engine::kRing && e == hipSuccess; ++i) {
