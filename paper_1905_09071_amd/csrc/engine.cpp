@@ -208,7 +208,7 @@ bool Engine::setup_device(Request& r) {
   r.has_dev = true;
   char* d = dev_base + r.dev_off;
   const char* h = host_base + r.host_off;
-  (void)hipMemcpyAsync(d, h, r.lay.upload, hipMemcpyHostToDevice, stream);
+  if (hipMemcpyAsync(d, h, r.lay.upload, hipMemcpyHostToDevice, stream) != hipSuccess) r.status = AGG_EHIP;
   r.h_out = (const double*)(h + r.lay.o_out);
   bind_shared(r.im, d, &r.st);
   r.st.tab = &r.tab;
@@ -266,7 +266,7 @@ void Engine::admit() {
       queue.pop_front();
     }
     r->t_admit = now_s();
-    if (r->nsteps == 0 || r->status != AGG_PENDING) {   // nothing to integrate, or no event
+    if (r->nsteps == 0 || r->status != AGG_PENDING) {   // nothing to integrate, or set-up failed
       if (r->status == AGG_PENDING) r->status = AGG_OK;
       r->t_finish = now_s();
       release(*r);
