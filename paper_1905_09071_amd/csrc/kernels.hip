@@ -412,7 +412,7 @@ template <int M2, bool LEAN> struct RowThreads {
 };
 
 template <class T, int M2, bool LEAN>
-__global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 5 : 1) void row_kernel(LaunchArgs a) {
+__global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void row_kernel(LaunchArgs a) {
   constexpr int NT = RowThreads<M2, LEAN>::value;
   constexpr bool TW_LDS = M2 <= 512;
   // transforms per register pass: 2048 values for 256 threads, twice that for
