@@ -158,7 +158,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="states of the batched C3 line (0 = skip)")
     ap.add_argument("--c5", type=int, default=1, help="run the D=5 N=2^20 batch-64 line (0 = skip)")
     ap.add_argument("--quick", action="store_true",
-                    help="profiling aid: time only the primary precision, no pass timing, no other lines")
+                    help="profiling aid: time only the primary precision (on --batch states if > 0), "
+                         "no pass timing, no other lines")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="profiling aid: also copy a float64 tensor of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -198,14 +199,16 @@ def main():
     order = [args.prec] + [p for p in ("fp64", "fp32", "fp32c") if p != args.prec]
     if args.quick:
         order = [args.prec]
+    # --quick with --batch B > 0 times the primary precision on B states instead
+    qb = args.batch if (args.quick and args.batch > 0) else 1
     for prec in order:
-        plan = agg.Plan(D, N, c["kernel"], prec)
-        n = torch.tensor(c["n0"], dtype=torch.float64, device="cuda:0")
+        plan = agg.Plan(D, N, c["kernel"], prec, batch=qb)
+        n = torch.tensor(np.tile(c["n0"], qb), dtype=torch.float64, device="cuda:0")
         t_gpu, t_wall = time_steps(plan, n, dt, args.steps, args.warmup, torch)
-        rate = 2 * args.steps / t_gpu
+        rate = 2 * args.steps * qb / t_gpu
         if args.quick:
             results[prec] = dict(seconds=t_gpu, wall=t_wall, rhs_per_s=rate, passes_us={w: 1.0 for w in range(4)})
-            log(f"[bench] {prec}: {args.steps} steps in {t_gpu*1e3:.2f} ms -> {rate:.1f} RHS/s (quick)")
+            log(f"[bench] {prec}: {args.steps} steps of {qb} state(s) in {t_gpu*1e3:.2f} ms -> {rate:.1f} RHS/s (quick)")
             plan.close()
             del n
             continue
@@ -217,7 +220,8 @@ def main():
         del n
 
     if args.quick:
-        print(json.dumps({"quick": True, "prec": args.prec, "rhs_per_s": round(results[args.prec]["rhs_per_s"], 2)}))
+        print(json.dumps({"quick": True, "prec": args.prec, "batch": qb,
+                          "rhs_per_s": round(results[args.prec]["rhs_per_s"], 2)}))
         return
 
     # the plain fp64 reference evaluation (term by term, unshared, unfused)
