@@ -160,6 +160,35 @@ def test_rhs_c3_full_size(prec):
     assert np.max(np.abs(got[:300] - refp)) <= RHS_TOL[prec] * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_saturating_batch_c3(prec):
+    """A batch large enough to fill the GPU takes the lean row and column
+    variants (fewer registers, several workgroups per CU): C3 shape, 8 states,
+    RHS and one Heun step of sampled members against the oracle."""
+    D, N, B = 4, 65536, 8
+    k = synth.kernel_ballistic(D, N, 0.4)
+    states = np.stack([synth.n0_uniform_head(N, 40 + b, 16) for b in range(B)])
+    say(f"[batch-C3] B={B} prec={prec}")
+    got = gpu_rhs(D, N, k, states, prec, batch=B)
+    for b in (0, 5, 7):
+        e = rel(got[b], oracle_rhs(D, N, k, states[b], "conv"))
+        say(f"  member {b}: err={e:.3e}")
+        assert e <= RHS_TOL[prec]
+    plan = agg.Plan(D, N, k, prec=prec, batch=B)
+    nt = torch.tensor(states.reshape(-1), dtype=torch.float64, device=DEV)
+    h = 5e-4
+    plan.rk2_step(nt, h)
+    torch.cuda.synchronize()
+    after = nt.cpu().numpy().reshape(B, N)
+    plan.close()
+    for b in (2, 7):
+        rhs = lambda v: oracle.total_rhs(*oracle.rhs_conv(D, N, k, v))
+        ref = oracle.heun_solve(rhs, states[b], h, h)
+        e = rel(after[b], ref)
+        say(f"  heun member {b}: err={e:.3e}")
+        assert e <= RHS_TOL[prec]
+
+
 def test_rk2_step_vs_oracle_heun():
     D, N, dt = 4, 300, 1e-2
     k = synth.kernel_ballistic(D, N, 0.4)
