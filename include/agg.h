@@ -74,6 +74,9 @@ typedef struct {
 typedef struct agg_plan agg_plan;
 
 /* Build a plan for `batch` independent states that share one kernel set.
+ * Results are deterministic for a plan; plans of different batch sizes may
+ * group the binary64 loss-term dot sums differently (a plan whose launches
+ * would leave CUs idle narrows its column groups), so they agree to rounding.
  * Terms: 2 <= d <= D, each d at most once, any order; orders not listed are
  * absent.  The factors are copied (deduplicated by bitwise column equality)
  * into plan-owned device memory: the caller may free them on return.
@@ -146,7 +149,10 @@ agg_status agg_twiddles(int64_t P, double* out);
 /* ---- serving: continuous batching of whole solves ------------------------- */
 typedef struct {
   int32_t device;          /* HIP device ordinal                                 */
-  int64_t mem_budget;      /* device bytes the engine may hold (0 = 8 GiB)       */
+  int64_t mem_budget;      /* device bytes reserved at creation, from which every
+                              admitted request gets one block (0 = 8 GiB); a
+                              pinned host region of a quarter of it (64 MiB to
+                              2 GiB) is reserved for staging too                */
   int32_t max_slots;       /* concurrent solves on the device (0 = 256)          */
 } agg_engine_config;
 
@@ -158,14 +164,25 @@ typedef struct {
 
 typedef struct agg_engine agg_engine;
 
+/* cfg may be NULL (all defaults).  Errors: AGG_EINVAL (negative budget or slot
+ * count, no such device, out == NULL), AGG_ENOMEM (the reservations failed),
+ * AGG_EHIP. */
 agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out);
-/* Cancels pending and running requests; their tickets end AGG_ECANCELLED. */
+/* Stops the scheduler after the work already on the device; queued and running
+ * requests are dropped with the engine, and no ticket may be polled after this
+ * call.  NULL is a no-op. */
 agg_status agg_engine_destroy(agg_engine* e);
 
 /* Queue one solve n(0) = n0 -> n(t_end) (same time grid as agg_solve).  Host
- * pointers; factors and n0 are copied before return.  Never blocks on the GPU.
+ * pointers; the calling thread builds the request's tables and stages them with
+ * n0 in the engine's pinned region (or in pageable memory while that region is
+ * full), so factors and n0 may be reused on return.  Never blocks on the GPU.
+ * Requests are admitted in submission order as device memory frees up.  A
+ * result equals, bit for bit, the same request served alone by an engine.
+ * Thread-safe with agg_poll and other agg_submit calls.
  * Errors as agg_plan_create/agg_solve, plus AGG_ENOMEM when the request's
- * device footprint alone exceeds the engine budget. */
+ * footprint alone exceeds the device budget or the pinned region, and
+ * AGG_EINVAL when every order has rank 0. */
 agg_status agg_submit(agg_engine* e, int32_t D, int64_t N, const agg_term* terms,
                       int32_t nterms, const double* n0, double dt, double t_end,
                       agg_precision prec, uint64_t* ticket);
