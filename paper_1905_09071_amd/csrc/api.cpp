@@ -277,7 +277,6 @@ struct agg_plan {
   hipGraphExec_t gexec = nullptr;
   double* g_state = nullptr;
   double g_dt = 0.0;
-  bool graphs = true;
 };
 
 // Heun steps per captured graph of the time loop.
@@ -320,10 +319,6 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   p->batch = batch;
   p->stream = (hipStream_t)hip_stream;
   p->trivial = p->tab.u == 0;
-  {
-    const char* ng = std::getenv("AGG_NO_GRAPH");
-    p->graphs = !(ng && ng[0] == '1');
-  }
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
   if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
   if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
@@ -515,7 +510,7 @@ static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, 
     if ((rc = full_step(p, p->stream, n, dt))) return rc;
     s = 1;
   }
-  if (p->graphs && full - s >= kGraphSteps) {
+  if (full - s >= kGraphSteps) {
     if ((rc = step_graph(p, n, dt))) return rc;
     for (; s + kGraphSteps <= full; s += kGraphSteps) {
       hipError_t e = hipGraphLaunch(p->gexec, p->stream);
