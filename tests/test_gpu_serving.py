@@ -119,3 +119,24 @@ def test_fifo_admission_under_tight_budget():
     admits = [res[t][2].t_admit for t in tickets]
     assert all(res[t][0] == agg.AGG_OK for t in tickets)
     assert admits == sorted(admits)
+
+
+def test_nonfinite_request_is_isolated():
+    """A request stepped far outside Heun's stability interval blows up; it ends
+    AGG_ENONFINITE (state still returned) while the requests that share its
+    launches (same transform length) finish exactly as they do alone."""
+    reqs = synth.serving_requests(3, seed=21, t_end_range=(0.005, 0.02), log2n_range=(11, 11))
+    bad = dict(reqs[0])
+    bad["dt"], bad["t_end"] = 5.0, 5.0 * 30
+    eng = agg.Engine(0)
+    allr = [bad] + reqs
+    tickets = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], "fp64") for r in allr]
+    res = drain(eng, tickets, [r["N"] for r in allr])
+    eng.close()
+    rc, out, st = res[tickets[0]]
+    assert rc == agg.AGG_ENONFINITE and st.status == agg.AGG_ENONFINITE
+    assert not np.all(np.isfinite(out))
+    for r, t in zip(reqs, tickets[1:]):
+        rc, out, st = res[t]
+        assert rc == agg.AGG_OK
+        assert np.array_equal(out, served_alone(r, "fp64"))
