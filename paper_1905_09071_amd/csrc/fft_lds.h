@@ -127,6 +127,58 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int nfft, const cplx<T>*
   lds_barrier();
 }
 
+// The same stage reading from `src` and writing to a second buffer `dst`:
+// no barrier is needed between the reads and the writes, one after them.
+template <class T, int P, int R, int NS, int DIR, int NB, int STR, int NT>
+__device__ __forceinline__ void fft_stage_pp(const cplx<T>* src, cplx<T>* dst, int nfft,
+                                             const cplx<T>* __restrict__ tw) {
+  constexpr int BPF = P / R;
+  constexpr int TOT = NB * BPF;
+  constexpr int K = (TOT + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  const int nvalid = nfft * BPF;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    int bg = tid + kk * NT;
+    if (bg < nvalid) {
+      int f = bg / BPF, b = bg % BPF;
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[f * STR + lds_pad(b + r * BPF)];
+      int j = b % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          int e = j * r * (P / (NS * R));
+          v[r] = twiddle_apply<T, DIR>(v[r], tw[e]);
+        }
+      }
+      dftR<T, R, DIR>(v);
+      int base = (b / NS) * NS * R + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[f * STR + lds_pad(base + r * NS)] = cnorm(v[r]);
+    }
+  }
+  lds_barrier();
+}
+
+// Number of Stockham stages of a length-P transform with radices up to RMAX.
+__host__ __device__ constexpr int fft_nstages(int P, int RMAX) {
+  int n = 0;
+  for (int ns = 1; ns < P; ns *= (P / ns >= RMAX ? RMAX : P / ns)) ++n;
+  return n;
+}
+
+template <class T, int P, int NS, int DIR, int NB, int STR, int NT, int RMAX>
+__device__ __forceinline__ void fft_stages_pp(cplx<T>* a, cplx<T>* b, int nfft, const cplx<T>* __restrict__ tw) {
+  if constexpr (NS < P) {
+    constexpr int REM = P / NS;
+    constexpr int R = REM >= RMAX ? RMAX : REM;
+    fft_stage_pp<T, P, R, NS, DIR, NB, STR, NT>(a, b, nfft, tw);
+    fft_stages_pp<T, P, NS * R, DIR, NB, STR, NT, RMAX>(b, a, nfft, tw);
+  }
+}
+
 template <class T, int P, int NS, int DIR, int NB, int STR, int NT, int RMAX>
 __device__ __forceinline__ void fft_stages(cplx<T>* buf, int nfft, const cplx<T>* __restrict__ tw) {
   if constexpr (NS < P) {
@@ -151,6 +203,19 @@ __device__ __forceinline__ void fft_batch(cplx<T>* buf, int count, const cplx<T>
     int nf = count - c0 < NB ? count - c0 : NB;
     fft_stages<T, P, 1, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, nf, tw);
   }
+}
+
+// fft_batch with a second buffer `alt` of the same layout: one barrier per
+// stage instead of two.  The stages alternate between the buffers; the result
+// is in the returned one (buf or alt, by the parity of the stage count).
+template <class T, int P, int DIR, int NB, int STR, int NT = kThreads, int RMAX = 8>
+__device__ __forceinline__ cplx<T>* fft_batch_pp(cplx<T>* buf, cplx<T>* alt, int count,
+                                                 const cplx<T>* __restrict__ tw) {
+  for (int c0 = 0; c0 < count; c0 += NB) {
+    int nf = count - c0 < NB ? count - c0 : NB;
+    fft_stages_pp<T, P, 1, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, alt + c0 * STR, nf, tw);
+  }
+  return (fft_nstages(P, RMAX) & 1) ? alt : buf;
 }
 
 }  // namespace agg

@@ -147,6 +147,12 @@ __device__ __forceinline__ void load_table(cplx<T>* dst, const void* src) {
 // four-step twiddles) is requested in one round at the start, so a launch
 // costs about three memory round trips: descriptor, data, stores.
 // ---------------------------------------------------------------------------
+// Second transform buffer (one barrier per Stockham stage instead of two): a
+// gain for the long float-float stages of small launches; binary64 and binary32
+// lose more to the extra registers than the barrier costs (measured).
+template <class T, int M1, bool LEAN>
+constexpr bool kColPingPong = !LEAN && M1 < 2048 && std::is_same<T, ff>::value;
+
 // LEAN (used when a launch already fills the GPU): no factor columns or Heun
 // vectors held in registers, and a register budget that lets two workgroups
 // share a CU, so one workgroup's memory wait overlaps another's arithmetic.
@@ -163,6 +169,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* tw = (cplx<T>*)smem;
   cplx<T>* buf = tw + M1;
+  cplx<T>* alt = buf + (size_t)a.ub * GMAX * STR;
   __shared__ double red[NWAVE][kColBatch];
 
   const int M2 = a.M2, g = a.g, lgg = a.lgg;
@@ -256,7 +263,9 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   double s0[IPT], s1[IPT];   // state the forward pass weights, at sizes 2j, 2j+1
   if (inv) {
     lds_barrier();
-    fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, g, tw);
+    cplx<T>* ib = buf;   // inverse transforms' result
+    if constexpr (!kColPingPong<T, M1, LEAN>) fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, g, tw);
+    else ib = fft_batch_pp<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, alt, g, tw);
 
     // loss weight g_k = sum_c U_c(k) G_c
     double gk[IPT][2];
@@ -294,7 +303,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
       s1[it] = 0.0;
       if (idx < nitems) {
         int j1 = idx >> lgg, jl = idx & (g - 1);
-        cplx<T> wv = buf[jl * STR + lds_pad(j1)];
+        cplx<T> wv = ib[jl * STR + lds_pad(j1)];
         double y[2] = {Real<T>::to_d(wv.re), Real<T>::to_d(wv.im)};
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -378,7 +387,10 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     }
     lds_barrier();
     // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
-    fft_batch<T, M1, -1, GMAX * (M1 >= 2048 ? 2 : kColBatch), STR, NT, StageRadix<T>::value>(buf, nc * g, tw);
+    constexpr int FNB = GMAX * (M1 >= 2048 ? 2 : kColBatch);
+    cplx<T>* fb = buf;   // forward transforms' result
+    if constexpr (!kColPingPong<T, M1, LEAN>) fft_batch<T, M1, -1, FNB, STR, NT, StageRadix<T>::value>(buf, nc * g, tw);
+    else fb = fft_batch_pp<T, M1, -1, FNB, STR, NT, StageRadix<T>::value>(buf, alt, nc * g, tw);
     for (int q = 0; q < nc; ++q) {
 #pragma unroll
       for (int it = 0; it < IPT; ++it) {
@@ -386,7 +398,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
         if (idx < nitems) {
           int k1 = idx >> lgg, jl = idx & (g - 1);
           stg(Z1 + ((size_t)(cb + q) * M + (int64_t)k1 * M2 + j2_0 + jl),
-              cnorm(cmul(buf[(q * g + jl) * STR + lds_pad(k1)], wst[it])));
+              cnorm(cmul(fb[(q * g + jl) * STR + lds_pad(k1)], wst[it])));
         }
       }
     }
@@ -747,7 +759,7 @@ static hipError_t launch_col_v(const LaunchArgs& a, hipStream_t s, size_t smem, 
   static bool attr_done = false;   // raise the dynamic LDS cap once per instantiation
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute((const void*)col_kernel<T, M1, LEAN>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kColLdsBudget + 16384);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
     if (e != hipSuccess) return e;
     attr_done = true;
   }
@@ -758,14 +770,15 @@ static hipError_t launch_col_v(const LaunchArgs& a, hipStream_t s, size_t smem, 
 template <class T, int M1>
 static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
   constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
-  size_t smem = ((size_t)M1 + (size_t)a.ub * GMAX * lds_len(M1)) * sizeof(cplx<T>);
+  const size_t tbuf = (size_t)a.ub * GMAX * lds_len(M1);   // transform buffer
   dim3 grid(a.nslots * (a.M2 / a.g));
   // from M1 = 1024 the register cap of the lean variant (two workgroups per CU)
   // spills the per-item state to scratch; those launches keep every register
   if constexpr (M1 <= kLeanMaxM1) {
-    if (a.lean) return launch_col_v<T, M1, true>(a, s, smem, grid);
+    if (a.lean) return launch_col_v<T, M1, true>(a, s, ((size_t)M1 + tbuf) * sizeof(cplx<T>), grid);
   }
-  return launch_col_v<T, M1, false>(a, s, smem, grid);
+  constexpr int nbuf = kColPingPong<T, M1, false> ? 2 : 1;
+  return launch_col_v<T, M1, false>(a, s, ((size_t)M1 + nbuf * tbuf) * sizeof(cplx<T>), grid);
 }
 
 template <class T>
@@ -794,7 +807,10 @@ size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max) {
 int col_batch(int prec, int M1, int u, int nworkgroups) {
   size_t cs = prec == 1 ? 8 : 16;
   size_t gmax = 1024 / M1 > 0 ? 1024 / M1 : 1;
-  size_t per = gmax * lds_len(M1) * cs;
+  const bool lean = nworkgroups >= kLeanWorkgroups && M1 <= kLeanMaxM1;
+  // the float-float full variant keeps a second transform buffer below the
+  // longest columns
+  size_t per = gmax * lds_len(M1) * cs * ((lean || M1 >= 2048 || prec != 2) ? 1 : 2);
   long ub = ((long)kColLdsBudget - (long)(M1 * cs)) / (long)per;
   if (ub < 1) ub = 1;
   if (ub > kColBatch) ub = kColBatch;
@@ -806,11 +822,12 @@ int col_batch(int prec, int M1, int u, int nworkgroups) {
 }
 
 template <class T, int M2>
-static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s, size_t smem) {
-  // saturating launches trade registers for five resident work groups per CU;
+static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s) {
+  // saturating launches trade registers for several resident work groups per CU;
   // smaller ones keep every register (no spills) for the shortest chains
   constexpr bool kHasLean = M2 <= 512;
   const bool lean = kHasLean && (int64_t)a.nslots * (a.M1 / 2 + 1) >= kLeanWorkgroups;
+  const size_t smem = row_smem_bytes(sizeof(cplx<T>) == 8 ? 1 : 0, a.umax, a.M2, a.tab_max, a.coef_max);
   const void* fn = lean ? (const void*)row_kernel<T, M2, kHasLean> : (const void*)row_kernel<T, M2, false>;
   static bool attr_done[2] = {false, false};   // raise the dynamic LDS cap once per instantiation
   if (!attr_done[lean]) {
@@ -827,19 +844,19 @@ static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s, size_t smem) 
 }
 
 template <class T>
-static hipError_t launch_row_p(const LaunchArgs& a, hipStream_t s, size_t smem) {
+static hipError_t launch_row_p(const LaunchArgs& a, hipStream_t s) {
   switch (a.M2) {
-    case 2: return launch_row_t<T, 2>(a, s, smem);
-    case 4: return launch_row_t<T, 4>(a, s, smem);
-    case 8: return launch_row_t<T, 8>(a, s, smem);
-    case 16: return launch_row_t<T, 16>(a, s, smem);
-    case 32: return launch_row_t<T, 32>(a, s, smem);
-    case 64: return launch_row_t<T, 64>(a, s, smem);
-    case 128: return launch_row_t<T, 128>(a, s, smem);
-    case 256: return launch_row_t<T, 256>(a, s, smem);
-    case 512: return launch_row_t<T, 512>(a, s, smem);
-    case 1024: return launch_row_t<T, 1024>(a, s, smem);
-    case 2048: return launch_row_t<T, 2048>(a, s, smem);
+    case 2: return launch_row_t<T, 2>(a, s);
+    case 4: return launch_row_t<T, 4>(a, s);
+    case 8: return launch_row_t<T, 8>(a, s);
+    case 16: return launch_row_t<T, 16>(a, s);
+    case 32: return launch_row_t<T, 32>(a, s);
+    case 64: return launch_row_t<T, 64>(a, s);
+    case 128: return launch_row_t<T, 128>(a, s);
+    case 256: return launch_row_t<T, 256>(a, s);
+    case 512: return launch_row_t<T, 512>(a, s);
+    case 1024: return launch_row_t<T, 1024>(a, s);
+    case 2048: return launch_row_t<T, 2048>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -851,10 +868,9 @@ hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_row(int prec, const LaunchArgs& a, hipStream_t s) {
-  size_t smem = row_smem_bytes(prec, a.umax, a.M2, a.tab_max, a.coef_max);
-  if (prec == 0) return launch_row_p<double>(a, s, smem);
-  if (prec == 1) return launch_row_p<float>(a, s, smem);
-  return launch_row_p<ff>(a, s, smem);
+  if (prec == 0) return launch_row_p<double>(a, s);
+  if (prec == 1) return launch_row_p<float>(a, s);
+  return launch_row_p<ff>(a, s);
 }
 
 hipError_t launch_moments(const double* n, int64_t total, int64_t N, double* part, int nblocks,
