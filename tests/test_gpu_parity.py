@@ -333,3 +333,25 @@ def test_graph_replayed_time_loop_equals_eager_steps(prec):
             plan.rk2_step(b, dt)                       # eager launches
         torch.cuda.synchronize()
         assert torch.equal(a, b), f"trial {trial}"
+
+
+def test_batched_graph_solve_equals_single_solves():
+    """agg_solve of a batch replays its captured graphs over all states; each
+    member equals the same solve of that state alone (both launches narrow the
+    column group to one column at this size, so the arithmetic is identical)."""
+    D, N, B, dt = 3, 1000, 4, 1e-3
+    k = synth.kernel_ballistic(D, N, 0.3)
+    states = np.stack([synth.n0_random_dense(N, 90 + b, decay=0.01) for b in range(B)])
+    plan = agg.Plan(D, N, k, "fp64", batch=B)
+    nb = torch.tensor(states.reshape(-1), dtype=torch.float64, device=DEV)
+    plan.solve(nb, dt, 40 * dt, stats=False)
+    torch.cuda.synchronize()
+    plan.close()
+    got = nb.cpu().numpy().reshape(B, N)
+    single = agg.Plan(D, N, k, "fp64")
+    for b in range(B):
+        n1 = torch.tensor(states[b], dtype=torch.float64, device=DEV)
+        single.solve(n1, dt, 40 * dt, stats=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[b], n1.cpu().numpy()), f"member {b}"
+    single.close()
