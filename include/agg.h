@@ -73,7 +73,9 @@ typedef struct {
 
 typedef struct agg_plan agg_plan;
 
-/* Build a plan for `batch` independent states that share one kernel set.
+/* Build a plan for `batch` independent states that share one kernel set given
+ * by its CP factors (Sec. 1, CP remark: the right-hand side then costs
+ * O(N D R log N) through FFT convolutions).
  * Results are deterministic for a plan; plans of different batch sizes may
  * group the binary64 loss-term dot sums differently (a plan whose launches
  * would leave CUs idle narrows its column groups), so they agree to rounding.
@@ -111,7 +113,9 @@ typedef struct {
   int64_t nonfinite;    /* count of non-finite entries of the final state       */
 } agg_solve_stats;
 
-/* Integrate n from t = 0 to t_end with step dt in place.  Time grid: the step
+/* Integrate n from t = 0 to t_end with step dt in place by repeated Heun steps
+ * (Sec. 3, as agg_rk2_step; full steps are replayed from captured HIP graphs of
+ * 16 steps, which compute exactly what eager steps compute).  Time grid: the step
  * count is round(t_end/dt) when t_end/dt is within 1e-9 (relative) of an
  * integer, else ceil(t_end/dt) with the last step shortened to reach t_end;
  * t_end = 0 takes no step.  With st == NULL the call is asynchronous.  With st
