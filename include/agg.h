@@ -48,7 +48,7 @@ enum {
   AGG_ENONFINITE = -4,    /* non-finite factor, initial value or final state    */
   AGG_ENOTFOUND = -5,     /* unknown ticket                                     */
   AGG_ECANCELLED = -6,    /* request cancelled (engine destroyed)               */
-  AGG_EUNSUPPORTED = -7   /* valid but beyond this build's limits (size, u)     */
+  AGG_EUNSUPPORTED = -7   /* valid but beyond the library's limits (size, u)   */
 };
 
 /* Arithmetic of the spectral path.  AGG_FP32C carries float-float (hi+lo)
