@@ -212,3 +212,16 @@ def test_planted_mistakes_are_caught(mutation):
     pm, qm = fn(D, N, kern, n)
     caught |= _rel(oracle.total_rhs(pm, qm), oracle.total_rhs(pd, qd)) > 1e-10
     assert caught
+
+
+def test_heun_step_is_heun_not_midpoint():
+    """One step of y' = y^2 from y = 1 with h = 0.1, worked by hand: Heun gives
+    1 + 0.05 (1 + 1.1^2) = 1.1105 (explicit midpoint would give 1.11025, Euler
+    1.1); every two-stage second-order method agrees on linear problems, so a
+    nonlinear one pins the stages.  The GPU path's Heun stages are checked
+    against this oracle."""
+    y = oracle.heun_solve(lambda v: v * v, np.array([1.0]), 0.1, 0.1)
+    assert abs(y[0] - 1.1105) < 1e-15
+    y2 = oracle.heun_solve(lambda v: v * v, np.array([1.0]), 0.1, 0.2)
+    y1 = 1.1105
+    assert abs(y2[0] - (y1 + 0.05 * (y1 ** 2 + (y1 + 0.1 * y1 ** 2) ** 2))) < 1e-15
