@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64", "fp32"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU sample budget (0 = skip)")
-    ap.add_argument("--serving", type=int, default=64, help="requests in the serving sample (0 = skip)")
+    ap.add_argument("--serving", type=int, default=512, help="requests in the serving sample (0 = skip)")
     ap.add_argument("--batch", type=int, default=64, help="states of the batched C3 line (0 = skip)")
     ap.add_argument("--c5", type=int, default=1, help="run the D=5 N=2^20 batch-64 line (0 = skip)")
     ap.add_argument("--quick", action="store_true",
