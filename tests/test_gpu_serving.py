@@ -140,3 +140,16 @@ def test_nonfinite_request_is_isolated():
         rc, out, st = res[t]
         assert rc == agg.AGG_OK
         assert np.array_equal(out, served_alone(r, "fp64"))
+
+
+def test_destroy_with_requests_in_flight():
+    """Destroying the engine while requests are queued and running returns
+    after the work already on the device, and a new engine serves normally."""
+    reqs = synth.serving_requests(6, seed=31, t_end_range=(0.02, 0.05), log2n_range=(12, 13))
+    eng = agg.Engine(0)
+    for r in reqs:
+        eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], "fp64")
+    t0 = time.time()
+    eng.close()
+    assert time.time() - t0 < 30.0
+    assert np.array_equal(served_alone(reqs[0], "fp64"), served_alone(reqs[0], "fp64"))
