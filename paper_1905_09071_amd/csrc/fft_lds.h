@@ -162,10 +162,11 @@ __device__ __forceinline__ void fft_stage_pp(const cplx<T>* src, cplx<T>* dst, i
   lds_barrier();
 }
 
-// Number of Stockham stages of a length-P transform with radices up to RMAX.
-__host__ __device__ constexpr int fft_nstages(int P, int RMAX) {
+// Number of Stockham stages of a length-P transform with radices up to RMAX,
+// from span NS0 on.
+__host__ __device__ constexpr int fft_nstages(int P, int RMAX, int NS0 = 1) {
   int n = 0;
-  for (int ns = 1; ns < P; ns *= (P / ns >= RMAX ? RMAX : P / ns)) ++n;
+  for (int ns = NS0; ns < P; ns *= (P / ns >= RMAX ? RMAX : P / ns)) ++n;
   return n;
 }
 
@@ -197,25 +198,28 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, int nfft, const cplx<T>
 // RMAX: largest radix per stage.  Radix 8 needs the fewest LDS passes (best
 // when many workgroups share a CU); radix 4 gives shorter per-thread chains and
 // more parallel butterflies (best when one workgroup per CU is latency-bound).
-template <class T, int P, int DIR, int NB, int STR, int NT = kThreads, int RMAX = 8>
+// NS0 > 1 starts after the first stage (the caller has written that stage's
+// output itself, e.g. the broadcast of an input whose nonzeros all fall in
+// the first radix-R block).
+template <class T, int P, int DIR, int NB, int STR, int NT = kThreads, int RMAX = 8, int NS0 = 1>
 __device__ __forceinline__ void fft_batch(cplx<T>* buf, int count, const cplx<T>* __restrict__ tw) {
   for (int c0 = 0; c0 < count; c0 += NB) {
     int nf = count - c0 < NB ? count - c0 : NB;
-    fft_stages<T, P, 1, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, nf, tw);
+    fft_stages<T, P, NS0, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, nf, tw);
   }
 }
 
 // fft_batch with a second buffer `alt` of the same layout: one barrier per
 // stage instead of two.  The stages alternate between the buffers; the result
 // is in the returned one (buf or alt, by the parity of the stage count).
-template <class T, int P, int DIR, int NB, int STR, int NT = kThreads, int RMAX = 8>
+template <class T, int P, int DIR, int NB, int STR, int NT = kThreads, int RMAX = 8, int NS0 = 1>
 __device__ __forceinline__ cplx<T>* fft_batch_pp(cplx<T>* buf, cplx<T>* alt, int count,
                                                  const cplx<T>* __restrict__ tw) {
   for (int c0 = 0; c0 < count; c0 += NB) {
     int nf = count - c0 < NB ? count - c0 : NB;
-    fft_stages_pp<T, P, 1, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, alt + c0 * STR, nf, tw);
+    fft_stages_pp<T, P, NS0, DIR, NB, STR, NT, RMAX>(buf + c0 * STR, alt + c0 * STR, nf, tw);
   }
-  return (fft_nstages(P, RMAX) & 1) ? alt : buf;
+  return (fft_nstages(P, RMAX, NS0) & 1) ? alt : buf;
 }
 
 }  // namespace agg

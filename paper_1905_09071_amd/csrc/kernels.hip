@@ -152,6 +152,10 @@ __device__ __forceinline__ void load_table(cplx<T>* dst, const void* src) {
 // lose more to the extra registers than the barrier costs (measured).
 template <class T, int M1, bool LEAN>
 constexpr bool kColPingPong = !LEAN && M1 < 2048 && std::is_same<T, ff>::value;
+// Forward transforms that skip a broadcast-only first stage (see the column
+// pass): enabled where the variant measured faster with it.
+template <class T, bool LEAN>
+constexpr bool kColPrune = std::is_same<T, ff>::value ? !LEAN : (std::is_same<T, double>::value && LEAN);
 
 // LEAN (used when a launch already fills the GPU): no factor columns or Heun
 // vectors held in registers, and a register budget that lets two workgroups
@@ -345,6 +349,23 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
 #pragma unroll
   for (int it = 0; it < IPT; ++it) wst[it] = cmul(wsh[it], wsl[it]);
   cplx<T>* Z1 = (cplx<T>*)sd.Z1;
+  // Sizes 2(j2 + M2 j1) + e exceed N for j1 > jmax.  When every nonzero input
+  // of the group's columns lies in the first block of the first radix-R1 stage
+  // (j1 < M1/R1), that stage only copies each input to its R1 outputs: the
+  // weighting writes them directly and the transform starts at its second stage.
+  constexpr int R1 = StageRadix<T>::value < M1 ? StageRadix<T>::value : M1;
+  const int64_t rest = N - 2 * (int64_t)j2_0;
+  const bool prune = kColPrune<T, LEAN> && (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
+  auto put = [&](int slot, int j1, cplx<T> v) {
+    if (prune) {
+      if (j1 < M1 / R1) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[slot * STR + lds_pad(R1 * j1 + r)] = v;
+      }
+    } else {
+      buf[slot * STR + lds_pad(j1)] = v;
+    }
+  };
   for (int cb = 0; cb < u; cb += a.ub) {
     const int nc = u - cb < a.ub ? u - cb : a.ub;
     // weighted columns x_c = U_c * state for c in [cb, cb+nc)
@@ -359,7 +380,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
             int j1 = idx >> lgg, jl = idx & (g - 1);
             double x0 = uc[q][it][0] * s0[it];
             double x1 = uc[q][it][1] * s1[it];
-            buf[((q - cb) * g + jl) * STR + lds_pad(j1)] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
+            put((q - cb) * g + jl, j1, cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)});
             dsum += x0 + x1;
           }
         }
@@ -378,7 +399,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
           int64_t s = pos[it];
           double x0 = (s >= 1 && s <= N) ? ldg(col + cix[it]) * s0[it] : 0.0;
           double x1 = (s + 1 <= N) ? ldg(col + (cix[it] + 1)) * s1[it] : 0.0;
-          buf[((c - cb) * g + jl) * STR + lds_pad(j1)] = cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)};
+          put((c - cb) * g + jl, j1, cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)});
           dsum += x0 + x1;
         }
       }
@@ -388,9 +409,15 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     lds_barrier();
     // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
     constexpr int FNB = GMAX * (M1 >= 2048 ? 2 : kColBatch);
+    constexpr int RF = StageRadix<T>::value;
     cplx<T>* fb = buf;   // forward transforms' result
-    if constexpr (!kColPingPong<T, M1, LEAN>) fft_batch<T, M1, -1, FNB, STR, NT, StageRadix<T>::value>(buf, nc * g, tw);
-    else fb = fft_batch_pp<T, M1, -1, FNB, STR, NT, StageRadix<T>::value>(buf, alt, nc * g, tw);
+    if constexpr (!kColPingPong<T, M1, LEAN>) {
+      if (prune) fft_batch<T, M1, -1, FNB, STR, NT, RF, R1>(buf, nc * g, tw);
+      else fft_batch<T, M1, -1, FNB, STR, NT, RF>(buf, nc * g, tw);
+    } else {
+      fb = prune ? fft_batch_pp<T, M1, -1, FNB, STR, NT, RF, R1>(buf, alt, nc * g, tw)
+                 : fft_batch_pp<T, M1, -1, FNB, STR, NT, RF>(buf, alt, nc * g, tw);
+    }
     for (int q = 0; q < nc; ++q) {
 #pragma unroll
       for (int it = 0; it < IPT; ++it) {
