@@ -408,7 +408,8 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     }
     lds_barrier();
     // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
-    constexpr int FNB = GMAX * (M1 >= 2048 ? 2 : kColBatch);
+    // lean launches transform one column per pass (ub = 1): one group of columns per register pass
+    constexpr int FNB = LEAN ? GMAX : GMAX * (M1 >= 2048 ? 2 : kColBatch);
     constexpr int RF = StageRadix<T>::value;
     cplx<T>* fb = buf;   // forward transforms' result
     if constexpr (!kColPingPong<T, M1, LEAN>) {
