@@ -240,7 +240,7 @@ def main():
     # N=2^20 batch of 64 states (transform length 2^23)
     batched = {}
     if args.batch > 0:
-        for prec in ("fp64", "fp32c"):
+        for prec in ("fp64", "fp32c", "fp32"):
             plan = agg.Plan(D, N, c["kernel"], prec, batch=args.batch)
             n = torch.tensor(np.tile(c["n0"], args.batch), dtype=torch.float64, device="cuda:0")
             bsteps = 20
