@@ -239,6 +239,7 @@ def main():
     # batched throughput: B states sharing the kernel (C3 shape) and the D=5,
     # N=2^20 batch of 64 states (transform length 2^23)
     batched = {}
+    roof_b = None
     if args.batch > 0:
         for prec in ("fp64", "fp32c", "fp32"):
             plan = agg.Plan(D, N, c["kernel"], prec, batch=args.batch)
@@ -247,6 +248,15 @@ def main():
             t_b, _ = time_steps(plan, n, dt, bsteps, 2, torch)
             batched[prec] = round(2 * bsteps * args.batch / t_b, 1)
             log(f"[bench] C3 batch {args.batch} {prec}: {2 * bsteps * args.batch / t_b:.1f} RHS/s")
+            if prec == args.prec:
+                # the same byte model at saturation: B states per launch
+                bp = {w: plan.profile_pass(n, w, reps=20) for w in (1, 3)}
+                wd = max(bp, key=bp.get)
+                byts = pass_bytes(wd, N, u, M, PREC_BYTES[prec]) * args.batch
+                ach = byts / (bp[wd] * 1e-6) / 1e9
+                roof_b = {"batch": args.batch, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": PASS_NAMES[wd],
+                          "bytes_per_launch": byts, "us_per_launch": round(bp[wd], 3)}
             plan.close()
             del n
             torch.cuda.empty_cache()
@@ -314,6 +324,7 @@ def main():
         "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,
+        "roofline_batched": roof_b,
         "cpu_baseline": cpu,
         "serving": serving,
     }
