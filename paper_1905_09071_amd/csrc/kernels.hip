@@ -79,12 +79,30 @@ __device__ __forceinline__ cplx<T> twL(const LaunchArgs& a, int64_t e) {
   return cmul(ldg(hi + (e >> a.b)), ldg(lo + (e & mask)));
 }
 
-// Sum over the 64 lanes of a wavefront (xor butterfly: every lane ends with the
-// same value, fixed order, so the result is reproducible).
+// One data-parallel-primitive move of a binary64 value (both 32-bit halves);
+// lanes without a source (or outside ROW_MASK) receive 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order (reproducible), with
+// register-to-register lane moves: pairs, quads, rows of 16 (row_shr 4 and 8
+// leave the row sum in lane 15), then rows 1 and 3 take lane 15 of the row
+// below and rows 2-3 lane 31, leaving the total in lane 63, which is read back
+// into every lane.  The whole wavefront must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<0xb1>(v);          // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);          // quad_perm [2,3,0,1]
+  v += dpp_move<0x114>(v);         // row_shr:4
+  v += dpp_move<0x118>(v);         // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // The same value in every lane, held in scalar registers: a pointer that is
