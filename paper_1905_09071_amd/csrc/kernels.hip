@@ -116,14 +116,15 @@ template <class T> __device__ __forceinline__ const __attribute__((address_space
 }
 __device__ __forceinline__ int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// The value held by the neighbouring lane (lane ^ 1), word by word.
+// The value held by the neighbouring lane (lane ^ 1), word by word, through a
+// DPP quad permute (a register move, no LDS round trip).
 template <class T> __device__ __forceinline__ cplx<T> lane_swap1(cplx<T> v) {
   static_assert(sizeof(cplx<T>) % 4 == 0, "whole 32-bit words");
   constexpr int W = sizeof(cplx<T>) / 4;
   int w[W];
   __builtin_memcpy(w, &v, sizeof(v));
 #pragma unroll
-  for (int i = 0; i < W; ++i) w[i] = __shfl_xor(w[i], 1, 64);
+  for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_mov_dpp(w[i], 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
   cplx<T> r;
   __builtin_memcpy(&r, w, sizeof(r));
   return r;
