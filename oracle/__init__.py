@@ -9,6 +9,8 @@ modelling multi-particle interactions"):
                    truncated linear convolutions (Sec. 1, CP remark)
 * ``rhs_fft``      the CP-FFT method of the Sec. 1 CP remark with numpy's FFT as a
                    library step, one product of spectra per (d, r)
+* ``rhs_sum_kernel`` the definitions specialised to kernels that depend on the
+                   total size only (no factorisation involved)
 * ``heun_solve``   explicit second-order Runge-Kutta (Heun) time stepping (Sec. 3)
 * closed forms     constant-kernel zeroth moment, binary constant kernel
 * ``plan_tables``  the written integer plan rules, implemented independently
@@ -24,3 +26,4 @@ from .heun import heun_solve, time_grid  # noqa: F401
 from .closed_forms import (m0_constant_kernel_d3, m0_rhs_constant_kernel,  # noqa: F401
                            binary_constant_monodisperse, scalar_heun)
 from .plan import plan_tables  # noqa: F401
+from .sum_kernel import rhs_sum_kernel  # noqa: F401

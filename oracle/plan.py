@@ -19,15 +19,23 @@ P5  Loss terms: for each (d, r) the key is (d, id of mode d, ascending-sorted id
     Coefficient = multiplicity / (d-1)!.
 P6  Two-pass split: lg = log2 M; M1 = 2^ceil(lg/2), M2 = M/M1.  With cs = 16
     bytes per stored complex (fp64, fp32c) or 8 (fp32): while u*2*M2*cs > 64 KiB
-    and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048 or
-    u*2*M2*cs > 144 KiB.
+    and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048.
 P7  Column tile: g = min(M2, max(1, 1024 / M1)) adjacent columns per workgroup.
+P8  Row-pass chunks, only when u*2*M2*cs > 144 KiB after P6 (the combine cannot
+    hold every column's two rows at once): cmax = floor(148 KiB / (2*(M2 +
+    M2/16)*cs)) columns per chunk (rows padded by one slot in 16 in LDS).  Gain terms are visited in the order of their ascending
+    tuple of distinct ids, ties kept in P4 order; a chunk takes the next term
+    while the union of its distinct ids and the term's stays within cmax, else
+    the chunk closes and a new one starts with that term.  Unsupported if a
+    single term has more than cmax distinct ids.  A chunk lists its ids
+    ascending and its terms by P4 position, in visiting order.
 
 Flat table (int64), as exported for comparison:
     [L, M1, M2, g, u, Tp, Tq, De,
      colmap in scan order (one id per (d, m, r)),
      per gain term:  d, multiplicity, ids[d],
-     per loss term:  d, multiplicity, kmode id, ids[d-1]]
+     per loss term:  d, multiplicity, kmode id, ids[d-1],
+     nchunks (0 without P8), per chunk: ncols, nterms, ids[ncols], terms[nterms]]
 """
 from __future__ import annotations
 
@@ -91,14 +99,34 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = 
     while u * 2 * M2 * cs > 65536 and M1 < 2048:
         M1 *= 2
         M2 //= 2
-    if M1 > 2048 or u * 2 * M2 * cs > 147456:
-        raise Unsupported(f"no two-pass split for L={L} with u={u} columns")
+    if M1 > 2048:
+        raise Unsupported(f"no two-pass split for L={L}")
     g = min(M2, max(1, 1024 // M1))
+
+    chunks = []
+    if u * 2 * M2 * cs > 147456:
+        cmax = 151552 // (2 * (M2 + M2 // 16) * cs)
+        order = sorted(range(len(pterms)), key=lambda t: (tuple(sorted(set(pterms[t][0]))), t))
+        cols, terms = set(), []
+        for t in order:
+            need = set(pterms[t][0])
+            if len(need) > cmax:
+                raise Unsupported(f"a gain term has {len(need)} distinct columns; a chunk holds {cmax}")
+            if terms and len(cols | need) > cmax:
+                chunks.append((sorted(cols), terms))
+                cols, terms = set(), []
+            cols |= need
+            terms.append(t)
+        if terms:
+            chunks.append((sorted(cols), terms))
 
     flat = [L, M1, M2, g, u, len(pterms), len(qterms), De] + colmap
     for key, mult in pterms:
         flat += [len(key), mult] + list(key)
     for (d, km, others), mult in qterms:
         flat += [d, mult, km] + list(others)
+    flat.append(len(chunks))
+    for cols, terms in chunks:
+        flat += [len(cols), len(terms)] + cols + terms
     return dict(L=L, M=M, M1=M1, M2=M2, g=g, u=u, De=De, colmap=colmap,
-                pterms=pterms, qterms=qterms, flat=np.array(flat, dtype=np.int64))
+                pterms=pterms, qterms=qterms, chunks=chunks, flat=np.array(flat, dtype=np.int64))

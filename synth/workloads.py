@@ -21,7 +21,7 @@ __all__ = [
     "kernel_additive", "kernel_random", "kernel_random_symmetric",
     "kernel_generalized_brownian", "n0_monodisperse", "n0_exponential",
     "n0_uniform_head", "n0_random_dense", "CONFIGS", "config", "build_kernel", "build_n0",
-    "serving_requests",
+    "serving_requests", "sum_kernel_values", "kernel_expsum",
 ]
 
 
@@ -129,6 +129,29 @@ def kernel_generalized_brownian(N: int, mus) -> np.ndarray:
         for j in range(d):
             U[sig[j], r] = s ** mus[j]
     return U
+
+
+def sum_kernel_values(smin: int, smax: int, power: float = 0.5) -> np.ndarray:
+    """Values f(s) = s**power for the integers s in [smin, smax]: the kernel
+    C^(d)(i) = (i_1 + ... + i_d)**power depends on the total size only."""
+    return np.arange(smin, smax + 1, dtype=np.float64) ** power
+
+
+def kernel_expsum(D: int, N: int, alpha, w) -> dict:
+    """CP factors of C^(d)(i) = w_0 + sum_r w_r exp(-alpha_r (i_1 + ... + i_d)) for
+    every d in [2, D], rank R+1 per order: term 0 has the constant w_0 in mode 1
+    and ones elsewhere, term r has w_r exp(-alpha_r i) in mode 1 and
+    exp(-alpha_r i) in the other modes.  Returned per order as a list of d
+    arrays of shape (R+1, N); the modes share two arrays (W for mode 1, E for
+    the rest) and every order shares the same two."""
+    s = sizes(N)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    E = np.ones((alpha.size + 1, N), dtype=np.float64)
+    for r, a in enumerate(alpha):
+        E[r + 1] = np.exp(-a * s)
+    W = E * w[:, None]
+    return {d: [W] + [E] * (d - 1) for d in range(2, D + 1)}
 
 
 def n0_monodisperse(N: int) -> np.ndarray:

@@ -225,3 +225,73 @@ def test_heun_step_is_heun_not_midpoint():
     y2 = oracle.heun_solve(lambda v: v * v, np.array([1.0]), 0.1, 0.2)
     y1 = 1.1105
     assert abs(y2[0] - (y1 + 0.05 * (y1 ** 2 + (y1 + 0.1 * y1 ** 2) ** 2))) < 1e-15
+
+
+def _brute_sum_kernel(D, N, f, n):
+    """Literal sums of Sec. 1 with the dense kernel C_i = f(i_1 + ... + i_d)."""
+    import itertools
+    p = np.zeros((D + 1, N))
+    q = np.zeros((D + 1, N))
+    for d in range(2, D + 1):
+        for idx in itertools.product(range(1, N + 1), repeat=d):
+            s = sum(idx)
+            prod = math.prod(n[i - 1] for i in idx)
+            c = f(s)
+            if s <= N:
+                p[d, s - 1] += c * prod / math.factorial(d)
+            k = idx[-1]
+            q[d, k - 1] -= c * prod / math.factorial(d - 1)
+    return p, q
+
+
+@pytest.mark.parametrize("D,N,seed", [(2, 11, 1), (3, 8, 2), (4, 6, 3), (5, 5, 4)])
+def test_sum_kernel_identity_matches_brute_force(D, N, seed):
+    """p^(d) = f(k) (n^{*d})_k / d! and the grouped loss sum, against the literal
+    sums with a dense kernel tensor (no CP form involved)."""
+    f = lambda s: math.sqrt(s) + 0.25 * (s % 3)
+    n = synth.n0_random_dense(N, seed)
+    fv = np.array([f(s) if s > 0 else 0.0 for s in range(D * N + 1)])
+    pb, qb = _brute_sum_kernel(D, N, f, n)
+    ps, qs = oracle.rhs_sum_kernel(D, N, fv, n)
+    for d in range(2, D + 1):
+        scale = max(np.abs(pb[d]).max(), np.abs(qb[d]).max())
+        assert np.abs(ps[d] - pb[d]).max() <= 1e-14 * scale
+        assert np.abs(qs[d] - qb[d]).max() <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("D,N", [(3, 9), (5, 6)])
+def test_expsum_factors_give_the_sum_kernel(D, N):
+    """The CP factors of an exponential sum (synth.kernel_expsum) reproduce the
+    function of the total size: the literal CP sums equal the identity."""
+    alpha, w = np.array([0.05, 0.4, 1.3]), np.array([0.7, 2.0, -1.5, 0.25])
+    kern = {d: np.asarray(v) for d, v in synth.kernel_expsum(D, N, alpha, w).items()}
+    fv = np.array([w[0] + np.sum(w[1:] * np.exp(-alpha * s)) for s in range(D * N + 1)])
+    n = synth.n0_random_dense(N, 11)
+    pd, qd = oracle.rhs_direct(D, N, kern, n)
+    ps, qs = oracle.rhs_sum_kernel(D, N, fv, n)
+    for d in range(2, D + 1):
+        scale = max(np.abs(pd[d]).max(), np.abs(qd[d]).max())
+        assert np.abs(ps[d] - pd[d]).max() <= 1e-13 * scale
+        assert np.abs(qs[d] - qd[d]).max() <= 1e-13 * scale
+
+
+def test_sum_kernel_fft_branch_matches_direct_branch():
+    """The FFT branches of the identity (dense state) against direct sums: the
+    gain prefix against the short-support branch (outputs k < m only involve
+    sizes < m), and the loss sum through the identity
+    sum_k q_k^(d) = -1/(d-1)! sum_s f(s) (n^{*d})_s with np.convolve powers."""
+    D, N = 4, 6000
+    n = synth.n0_random_dense(N, 5, decay=1e-3)
+    fv = np.sqrt(np.arange(D * N + 1, dtype=np.float64))
+    p, q = oracle.rhs_sum_kernel(D, N, fv, n)
+    m = 40
+    ns = n.copy()
+    ns[m:] = 0.0
+    ps, qs = oracle.rhs_sum_kernel(D, N, fv, ns)
+    x = np.concatenate([[0.0], n])
+    power = x
+    for d in range(2, D + 1):
+        assert np.abs(p[d, :m] - ps[d, :m]).max() <= 1e-13 * np.abs(p[d]).max()
+        power = np.convolve(power, x)
+        expect = -np.dot(fv[:power.size], power) / math.factorial(d - 1)
+        assert abs(q[d].sum() - expect) <= 1e-12 * abs(expect)
