@@ -142,13 +142,46 @@ agg_status agg_profile_pass(agg_plan* plan, const double* n, int32_t pass, int32
  * agg_plan_tables writes the plan's integer tables as int64 (layout:
  * [L, M1, M2, g, u, Tp, Tq, De, column id per (d, m, r) in scan order d, m, r,
  *  per gain term: d, multiplicity, ids[d],
- *  per loss term: d, multiplicity, k-mode id, ids[d-1]])
+ *  per loss term: d, multiplicity, k-mode id, ids[d-1],
+ *  number of row-pass chunks H (0 when every column fits the row pass at once),
+ *  per chunk: ncols, nterms, column ids[ncols], gain-term indices[nterms]])
  * into out[0..cap) and its full length into *len.  AGG_EINVAL if cap is short
  * (len still set).  agg_twiddles writes exp(-2 pi i e / P) for e = 0..P-1 as
  * interleaved binary64 (re, im) pairs into out[0..2P) (P a power of two). */
 agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
                            agg_precision prec, int64_t* out, int64_t cap, int64_t* len);
 agg_status agg_twiddles(int64_t P, double* out);
+
+/* ---- host kernel compression (no device is touched) ------------------------
+ * For kernels that depend on the total size only, C^(d)_{i_1..i_d} =
+ * f(i_1 + ... + i_d), the paper knows no robust CP construction in general
+ * (Sec. 2, remark on the canonical format); this class has one through a 1-D
+ * exponential sum, because exp(-a (i_1+..+i_d)) = prod_m exp(-a i_m):
+ *     f(s) ~ w[0] + sum_{r=1..R} w[r] exp(-alpha[r-1] s),
+ * and order d then has CP rank R+1 with, for term r, the column
+ * w[r] exp(-alpha[r-1] i) in mode 1 and exp(-alpha[r-1] i) in modes 2..d
+ * (term 0: the constant w[0] in mode 1, ones elsewhere).  One fit over
+ * [2, D N] serves every order d <= D; the kernel error of order d is the fit
+ * error over [d, d N].
+ *   f       host, f[s - smin] = f(s) for every integer s in [smin, smax]
+ *   R       number of exponentials, 0..64
+ *   relative 0: minimise the absolute error; else the error relative to |f(s)|
+ *           (every f(s) must then be non-zero)
+ *   alpha   host out, R exponents (> 0, ascending)
+ *   w       host out, R+1 weights (w[0] the constant)
+ *   max_err host out, max over every integer s in [smin, smax] of |fit(s) - f(s)|,
+ *           divided by |f(s)| for a relative fit
+ * Exponents lie on a geometric grid whose ends are picked among a few
+ * multiples of 1/smax and 1/smin; weights come from least squares on a sample
+ * of the range (its first 1024 integers and 8192 geometric points), refined
+ * toward the smallest maximum error by iterative reweighting.  Weights of
+ * alternating sign and magnitudes above max|f| are normal: their cancellation
+ * costs accuracy in the lower precisions.
+ * Errors: AGG_EINVAL (NULL pointer, smin < 1, smax < smin, R outside [0, 64],
+ * a zero f(s) in a relative fit), AGG_ENONFINITE (a non-finite f value),
+ * AGG_EUNSUPPORTED (no fit found), AGG_ENOMEM. */
+agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax, int32_t R, int32_t relative,
+                          double* alpha, double* w, double* max_err);
 
 /* ---- serving: continuous batching of whole solves ------------------------- */
 typedef struct {

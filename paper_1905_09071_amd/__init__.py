@@ -15,22 +15,30 @@ from ._lib import (AGG_EINVAL, AGG_ENOMEM, AGG_ENONFINITE, AGG_ENOTFOUND, AGG_EU
                    AGG_OK, AGG_PENDING, AGG_MAX_D, PREC, AggError, agg_engine_config,
                    agg_request_stats, agg_solve_stats, agg_term, check, lib)
 
-__all__ = ["Plan", "Engine", "plan_tables", "twiddles", "AggError", "PREC", "make_terms"]
+__all__ = ["Plan", "Engine", "plan_tables", "twiddles", "expsum_fit", "AggError", "PREC", "make_terms"]
 
 
 def make_terms(D: int, N: int, kernel: dict):
-    """Build the agg_term array; returns (array, keepalive list)."""
+    """Build the agg_term array; returns (array, keepalive list).  The factors
+    of order d are an array of shape (d, R, N), or a list of d arrays of shape
+    (R, N) (modes may then share one array)."""
     items = sorted(kernel.items())
     arr = (agg_term * max(len(items), 1))()
     keep = []
     for t, (d, U) in enumerate(items):
-        U = np.asarray(U, dtype=np.float64)
-        if U.ndim != 3 or U.shape[0] != d or U.shape[2] != N:
-            raise ValueError(f"factors of order {d} must have shape (d, R, N) = ({d}, R, {N})")
+        modes = list(U) if isinstance(U, (list, tuple)) else None
+        if modes is None:
+            U = np.asarray(U, dtype=np.float64)
+            if U.ndim != 3 or U.shape[0] != d or U.shape[2] != N:
+                raise ValueError(f"factors of order {d} must have shape (d, R, N) = ({d}, R, {N})")
+            modes = [U[m] for m in range(d)]
+        if len(modes) != d or any(np.ndim(x) != 2 or np.shape(x)[1] != N or np.shape(x)[0] != np.shape(modes[0])[0]
+                                  for x in modes):
+            raise ValueError(f"factors of order {d} must be d arrays of shape (R, {N})")
         arr[t].d = d
-        arr[t].rank = U.shape[1]
+        arr[t].rank = np.shape(modes[0])[0]
         for m in range(d):
-            col = np.ascontiguousarray(U[m])
+            col = np.ascontiguousarray(modes[m], dtype=np.float64)
             keep.append(col)
             arr[t].U[m] = col.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return arr, len(items), keep
@@ -50,6 +58,20 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", plain: bool = 
                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.size, ctypes.byref(ln)))
     del keep
     return out[:ln.value]
+
+
+def expsum_fit(f: np.ndarray, smin: int, R: int, relative: bool = False):
+    """Exponential-sum fit of f on the integers smin .. smin+len(f)-1 (host):
+    returns (alpha[R], w[R+1], max_err); max_err is relative to |f| when
+    ``relative``."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    alpha = np.zeros(max(R, 1))
+    w = np.zeros(R + 1)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().agg_expsum_fit(f.ctypes.data_as(dp), int(smin), int(smin) + f.size - 1, int(R), int(bool(relative)),
+                               alpha.ctypes.data_as(dp), w.ctypes.data_as(dp), ctypes.byref(err)))
+    return alpha[:R], w, err.value
 
 
 def twiddles(P: int) -> np.ndarray:

@@ -29,6 +29,7 @@ SOURCES = [
     ("api.cpp", False),
     ("planner.cpp", False),
     ("engine.cpp", False),
+    ("compress.cpp", False),
 ]
 
 

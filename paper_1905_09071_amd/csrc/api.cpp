@@ -2,6 +2,7 @@
 // whole solves on one GPU.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -96,17 +97,38 @@ SharedImage make_shared_image(const PlanTables& T) {
   SharedImage im;
   const int64_t N = T.N;
   std::vector<int> p_off{0}, p_ids, q_off{0}, q_ids, q_km, p_from;
+  std::vector<int> ch_coff{0}, ch_cols, ch_toff{0};
   std::vector<double> coef;
-  for (size_t t = 0; t < T.p_ids.size(); ++t) {
-    for (int id : T.p_ids[t]) p_ids.push_back(id);
+  // gain terms in the order the row pass combines them: plan order, or chunk by
+  // chunk with ids local to the chunk (position in its column list)
+  std::vector<int> torder, tchunk;
+  std::vector<std::vector<int>> tids;
+  if (T.cmax == 0) {
+    for (size_t t = 0; t < T.p_ids.size(); ++t) { torder.push_back((int)t); tchunk.push_back(0); tids.push_back(T.p_ids[t]); }
+  } else {
+    for (size_t c = 0; c < T.ch_cols.size(); ++c) {
+      const std::vector<int>& cc = T.ch_cols[c];
+      for (int id : cc) ch_cols.push_back(id);
+      ch_coff.push_back((int)ch_cols.size());
+      for (int t : T.ch_terms[c]) {
+        std::vector<int> loc;
+        for (int id : T.p_ids[t]) loc.push_back((int)(std::lower_bound(cc.begin(), cc.end(), id) - cc.begin()));
+        torder.push_back(t); tchunk.push_back((int)c); tids.push_back(loc);
+      }
+      ch_toff.push_back((int)torder.size());
+    }
+  }
+  for (size_t i = 0; i < torder.size(); ++i) {
+    const int t = torder[i];
+    for (int id : tids[i]) p_ids.push_back(id);
     p_off.push_back((int)p_ids.size());
     coef.push_back((double)T.p_mult[t] / factorial((int)T.p_ids[t].size()));
     // a term whose ids start with all of the previous term's ids continues
     // that term's running product (same-order multiplications, fewer of them)
-    int from = p_off[t];
-    if (t > 0) {
-      const std::vector<int>& a = T.p_ids[t - 1];
-      const std::vector<int>& b = T.p_ids[t];
+    int from = p_off[i];
+    if (i > 0 && tchunk[i - 1] == tchunk[i]) {
+      const std::vector<int>& a = tids[i - 1];
+      const std::vector<int>& b = tids[i];
       if (a.size() < b.size() && std::equal(a.begin(), a.end(), b.begin())) from += (int)a.size();
     }
     p_from.push_back(from);
@@ -129,6 +151,10 @@ SharedImage make_shared_image(const PlanTables& T) {
   im.o_qids = put(q_ids);
   im.o_qkm = put(q_km);
   im.o_pfrom = put(p_from);
+  im.nch = (int)T.ch_cols.size();
+  im.o_chc = put(ch_coff);
+  im.o_chcols = put(ch_cols);
+  im.o_cht = put(ch_toff);
   im.ntab = (int)blob.size();
   im.Tp = (int)T.p_ids.size();
   im.Tq = (int)T.q_ids.size();
@@ -174,6 +200,7 @@ void bind_shared(const SharedImage& im, void* dev, SharedTables* st) {
   st->twLhi = b + im.o_twhi;
   st->Tp = im.Tp; st->Tq = im.Tq; st->ntab = im.ntab;
   st->o_pids = im.o_pids; st->o_qoff = im.o_qoff; st->o_qids = im.o_qids; st->o_qkm = im.o_qkm; st->o_pfrom = im.o_pfrom;
+  st->nch = im.nch; st->o_chc = im.o_chc; st->o_chcols = im.o_chcols; st->o_cht = im.o_cht;
 }
 
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st) {
@@ -219,6 +246,7 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   sd->cols = st.cols;
   sd->tab = st.tabs; sd->coef = st.coef; sd->ntab = st.ntab;
   sd->o_pids = st.o_pids; sd->o_qoff = st.o_qoff; sd->o_qids = st.o_qids; sd->o_qkm = st.o_qkm; sd->o_pfrom = st.o_pfrom;
+  sd->nch = st.nch; sd->o_chc = st.o_chc; sd->o_chcols = st.o_chcols; sd->o_cht = st.o_cht;
   sd->N = (int)T.N; sd->u = T.u; sd->Tp = st.Tp; sd->Tq = st.Tq;
   sd->mode = CM_NONE; sd->row_on = 0; sd->dt = 0.0;
   if (stride) *stride = s;
@@ -227,6 +255,14 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
 
 agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd) {
   return build_slots(T, st, arena, 1, sd, nullptr);
+}
+
+agg_status row_lds_check(const PlanTables& T, int ntab, int ncoef) {
+  const size_t need = T.cmax > 0 ? row_chunk_smem_bytes(T.prec, T.cmax, std::max(T.u, 1), T.M2, ntab, ncoef)
+                                 : row_smem_bytes(T.prec, std::max(T.u, 1), T.M2, ntab, ncoef);
+  if (need > kRowLdsLimit)
+    return set_error(AGG_EUNSUPPORTED, "the row pass's tables and spectra exceed the LDS of a workgroup");
+  return AGG_OK;
 }
 
 LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots,
@@ -243,6 +279,7 @@ LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc
   if (spread)
     while (a.g > 1 && (int64_t)nslots * (T.M2 / a.g) < kSpreadWorkgroups) a.g >>= 1;
   a.umax = std::max(T.u, 1);
+  a.cmax = T.cmax;
   a.ub = col_batch(T.prec, T.M1, T.u, nslots * (T.M2 / a.g));
   a.lean = nslots * (T.M2 / a.g) >= kLeanWorkgroups ? 1 : 0;
   a.lgg = 0;
@@ -320,6 +357,7 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   p->stream = (hipStream_t)hip_stream;
   p->trivial = p->tab.u == 0;
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
+  if ((rc = row_lds_check(p->tab, p->st.ntab, p->st.Tp + p->st.Tq))) goto fail;
   if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
   if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
   if ((rc = p->arena.alloc(sizeof(double) * p->tab.N * batch, (void**)&p->d_scratch))) goto fail;

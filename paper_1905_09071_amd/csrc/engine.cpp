@@ -3,10 +3,11 @@
 // A scheduler thread owns all device work.  Each request becomes a slot with
 // its own state, Heun buffers, spectra and tables in device memory, admitted in
 // FIFO order while its footprint fits in the free budget.  Running slots whose
-// plans share the launch geometry (L, M1, M2, g, precision) form a bucket; at
-// every tick each bucket gets ONE row launch and ONE column launch over all of
-// its slots, with each slot's stage (first forward pass, Heun stage 1, Heun
-// stage 2, last stage) carried in its device descriptor.  A slot therefore
+// plans share the launch geometry (L, M1, M2, g, precision, row-pass chunk
+// capacity) form a bucket; at every tick each bucket gets ONE row launch and
+// ONE column launch over all of its slots, with each slot's stage (first
+// forward pass, Heun stage 1, Heun stage 2, last stage) carried in its device
+// descriptor.  A slot therefore
 // computes exactly what it would compute alone: nothing in a slot's arithmetic
 // depends on its neighbours.  Requests that arrive while others run join at
 // the next tick; finished slots are copied out and their memory returned.
@@ -140,7 +141,7 @@ struct Request {
   std::vector<double> result;
 };
 
-using BucketKey = std::tuple<int64_t, int, int, int, int>;   // L, M1, M2, g, prec
+using BucketKey = std::tuple<int64_t, int, int, int, int, int>;   // L, M1, M2, g, prec, chunk cap
 
 struct Engine {
   agg_engine_config cfg{};
@@ -226,6 +227,7 @@ bool Engine::setup_device(Request& r) {
   s.coef = r.st.coef;
   s.ntab = r.st.ntab;
   s.o_pids = r.st.o_pids; s.o_qoff = r.st.o_qoff; s.o_qids = r.st.o_qids; s.o_qkm = r.st.o_qkm; s.o_pfrom = r.st.o_pfrom;
+  s.nch = r.st.nch; s.o_chc = r.st.o_chc; s.o_chcols = r.st.o_chcols; s.o_cht = r.st.o_cht;
   s.N = (int)r.tab.N; s.u = r.tab.u; s.Tp = r.st.Tp; s.Tq = r.st.Tq;
   if (!spare_events.empty()) {
     r.done_ev = spare_events.back();
@@ -293,7 +295,7 @@ void Engine::tick() {
   std::map<BucketKey, std::vector<Request*>> buckets;
   for (auto& rp : running) {
     const PlanTables& T = rp->tab;
-    buckets[BucketKey(T.L, T.M1, T.M2, T.g, T.prec)].push_back(rp.get());
+    buckets[BucketKey(T.L, T.M1, T.M2, T.g, T.prec, T.cmax)].push_back(rp.get());
   }
   struct Launch { int off, cnt, umax, tab_max, coef_max; Request* first; };
   std::vector<Launch> launches;
@@ -522,6 +524,7 @@ agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms
   Engine& g = E->eng;
   // the tables are built on the caller's thread, off the scheduler's path
   r->im = make_shared_image(r->tab);
+  if ((rc = row_lds_check(r->tab, r->im.ntab, r->im.Tp + r->im.Tq))) return rc;
   r->lay = request_layout(r->tab, r->im.bytes.size());
   if ((int64_t)r->lay.dev_total > g.cfg.mem_budget || r->lay.host_total > g.host.size)
     return set_error(AGG_ENOMEM, "request footprint exceeds the engine budget");

@@ -30,6 +30,7 @@ struct SharedTables {
   const int* tabs = nullptr;       // int blob (see SlotDesc)
   const double* coef = nullptr;    // coefficient blob
   int Tp = 0, Tq = 0, ntab = 0, o_pids = 0, o_qoff = 0, o_qids = 0, o_qkm = 0, o_pfrom = 0;
+  int nch = 0, o_chc = 0, o_chcols = 0, o_cht = 0;
   void *twP1 = nullptr, *twP2 = nullptr, *twLlo = nullptr, *twLhi = nullptr;
 };
 
@@ -38,6 +39,7 @@ struct SharedImage {
   std::vector<unsigned char> bytes;
   size_t o_cols = 0, o_tabs = 0, o_coef = 0, o_tw1 = 0, o_tw2 = 0, o_twlo = 0, o_twhi = 0;
   int Tp = 0, Tq = 0, ntab = 0, o_pids = 0, o_qoff = 0, o_qids = 0, o_qkm = 0, o_pfrom = 0;
+  int nch = 0, o_chc = 0, o_chcols = 0, o_cht = 0;
 };
 SharedImage make_shared_image(const PlanTables& T);
 void bind_shared(const SharedImage& im, void* dev, SharedTables* st);
@@ -48,6 +50,10 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st);
 agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd);
 size_t slot_bytes(const PlanTables& T);
+// Dynamic LDS a row-pass workgroup may take, and the check that a kernel set's
+// row pass fits (AGG_EUNSUPPORTED otherwise).
+constexpr size_t kRowLdsLimit = 160 * 1024 - 4096;
+agg_status row_lds_check(const PlanTables& T, int ntab, int ncoef);
 // spread: narrow the column group g below the plan's when the launch has fewer
 // column groups than CUs; every launch that shares a slot's partial dot
 // products must be built with the same choice and slot count.
@@ -63,6 +69,7 @@ hipError_t launch_heun(int stage, double* n, const double* k1, const double* k2,
                        int64_t total, hipStream_t s);
 hipError_t launch_zero(double* x, int64_t total, hipStream_t s);
 size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max);
+size_t row_chunk_smem_bytes(int prec, int cmax, int umax, int M2, int tab_max, int coef_max);
 int col_batch(int prec, int M1, int u, int nworkgroups);
 
 }  // namespace agg

@@ -44,11 +44,16 @@ struct SlotDesc {
   double* dots;           // u*ngroups partial dot products (column kernel -> row kernel)
   double* G;              // u loss-term weights of the current evaluation
   // term tables, one int blob: p_off[Tp+1] | p_ids | q_off[Tq+1] | q_ids | q_kmode[Tq] | p_from[Tp]
+  // | ch_coff[nch+1] | ch_cols | ch_toff[nch+1]
   // (p_from[t] > p_off[t]: gain term t extends term t-1, whose ids are its prefix)
-  // (offsets below), and one binary64 blob: p_coef[Tp] (mult/d!) | q_coef[Tq] (mult/(d-1)!)
+  // (offsets below), and one binary64 blob: p_coef[Tp] (mult/d!) | q_coef[Tq] (mult/(d-1)!).
+  // With row-pass chunks (nch > 0) the gain terms are listed chunk by chunk,
+  // chunk h owning terms [ch_toff[h], ch_toff[h+1]) and columns
+  // ch_cols[ch_coff[h] .. ch_coff[h+1]), and p_ids hold positions in that list.
   const int* tab;
   const double* coef;
   int ntab, o_pids, o_qoff, o_qids, o_qkm, o_pfrom;
+  int nch, o_chc, o_chcols, o_cht;
   int N, u, Tp, Tq;
   int mode;               // per-slot column mode (when the launch mode is < 0)
   int row_on;             // per-slot row pass switch (when the launch mode is < 0)
@@ -79,6 +84,7 @@ struct LaunchArgs {
   int lgg;                // log2(g)
   int64_t L;
   int umax;               // largest u among the slots (row kernel LDS sizing)
+  int cmax;               // > 0: slots combine chunk by chunk, at most cmax columns each
   int ub;                 // forward columns transformed together in the column pass
   int tab_max;            // largest term-table int blob among the slots
   int coef_max;           // largest coefficient blob (Tp + Tq) among the slots

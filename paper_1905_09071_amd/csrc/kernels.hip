@@ -739,6 +739,206 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
 }
 
 // ---------------------------------------------------------------------------
+// Row pass in chunks, for kernel sets whose distinct columns do not all fit in
+// LDS at the row length (many ranks at the longest transforms).  Work item and
+// result are those of row_kernel.  The gain terms come grouped into chunks of
+// at most a.cmax columns; per chunk the work item loads, transforms and unpacks
+// that chunk's columns only and adds the chunk's terms to per-thread sums of
+// the combined spectrum, which stay in registers across chunks.  The inverse
+// transform and the loss-term weights follow the last chunk.  A slot without
+// chunk tables runs as one chunk of all its columns.
+// LDS: M2 twiddles (M2 <= 512), a.cmax*2 rows, a.cmax Nyquist values, the
+// per-wave partial dots and the u dot products.
+// ---------------------------------------------------------------------------
+template <class T, int M2>
+__global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_kernel(LaunchArgs a) {
+  constexpr int NT = RowThreads<M2, false>::value;
+  constexpr bool TW_LDS = M2 <= 512;
+  constexpr int NB = (M2 >= 1024 && NT > kThreads) ? 4096 / M2 : ((2048 / M2) > 0 ? 2048 / M2 : 1);
+  constexpr int STR = lds_len(M2);
+  constexpr int NWAVE = NT / 64;
+  constexpr int UPT = (M2 + NT - 1) / NT;       // combine units (bin pairs) per thread
+  constexpr int VPT = (2 * M2 + NT - 1) / NT;   // output values per thread
+  extern __shared__ __align__(16) unsigned char smem[];
+
+  const int M1 = a.M1;
+  const int nwork = M1 / 2 + 1;
+  const int slot = blockIdx.x / nwork;
+  const int k1 = blockIdx.x - slot * nwork;
+  const SlotDesc sd = slot_desc(a, slot);
+  const int row_on = a.mode >= 0 ? 1 : sd.row_on;
+  if (!row_on) return;
+  const int u = sd.u;
+  const int64_t M = (int64_t)M1 * M2;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+
+  cplx<T>* twl = (cplx<T>*)smem;                          // M2 when TW_LDS
+  const cplx<T>* tw = TW_LDS ? twl : (const cplx<T>*)a.twP2;
+  cplx<T>* X = twl + (TW_LDS ? M2 : 0);                   // cmax*2 rows
+  cplx<T>* nyq = X + (size_t)a.cmax * 2 * STR;            // cmax
+  double* red = (double*)(nyq + a.cmax);                  // NWAVE * umax
+  double* sdot = red + NWAVE * a.umax;                    // umax
+
+  const int nrows = (k1 == 0 || 2 * k1 == M1) ? 1 : 2;
+  auto row_of = [&](int rr) { return rr ? M1 - k1 : k1; };
+  const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
+  if (TW_LDS) load_table<T, M2, NT>(twl, a.twP2);
+  cplx<T> wk[UPT];   // w_L^k of this thread's combine units
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) {
+    const int unit = tid + i * NT;
+    wk[i] = unit < nunits ? twL<T>(a, k1 + (int64_t)M1 * unit) : czero<T>();
+  }
+  if (k1 == 0) {   // partial dots of the column pass -> per-wave sums
+    const int ngroups = M2 / a.g;
+    for (int c = 0; c < u; ++c) {
+      double sacc = 0.0;
+      for (int q = tid; q < ngroups; q += NT) sacc += ldg(sd.dots + ((size_t)c * ngroups + q));
+      sacc = wave_sum(sacc);
+      if (lane == 0) red[wave * a.umax + c] = sacc;
+    }
+  }
+
+  const bool chunked = sd.nch > 0;
+  const int nch = chunked ? uniform_int(sd.nch) : 1;
+  const auto chc = uniform_ptr(sd.tab + sd.o_chc);
+  const auto chcols = uniform_ptr(sd.tab + sd.o_chcols);
+  const auto cht = uniform_ptr(sd.tab + sd.o_cht);
+  const auto poff = uniform_ptr(sd.tab);
+  const auto pids = uniform_ptr(sd.tab + sd.o_pids);
+  const auto pcoef = uniform_ptr(sd.coef);
+  const auto pfrom = uniform_ptr(sd.tab + sd.o_pfrom);
+  const cplx<T>* Z1 = (const cplx<T>*)sd.Z1;
+  auto pair_of = [&](int unit, int& iB, int& rB) {
+    if (k1 == 0) { iB = (M2 - unit) & (M2 - 1); rB = 0; }
+    else if (nrows == 1) { iB = M2 - 1 - unit; rB = 0; }
+    else { iB = M2 - 1 - unit; rB = 1; }
+  };
+
+  cplx<T> YA[UPT], YB[UPT];
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) YA[i] = YB[i] = czero<T>();
+  for (int h = 0; h < nch; ++h) {
+    const int c0 = chunked ? chc[h] : 0;
+    const int nc = chunked ? chc[h + 1] - c0 : uniform_int(u);
+    const int t0 = chunked ? cht[h] : 0;
+    const int t1 = chunked ? cht[h + 1] : uniform_int(sd.Tp);
+    lds_barrier();   // the previous chunk's combine is done with X
+    const int nload = nc * nrows * M2;
+    for (int idx = tid; idx < nload; idx += NT) {
+      const int cr = idx / M2, k2 = idx - cr * M2;
+      const int c = cr / nrows, rr = cr - c * nrows;
+      const int gc = chunked ? chcols[c0 + c] : c;
+      X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)gc * M + (int64_t)row_of(rr) * M2 + k2));
+    }
+    lds_barrier();
+    fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, nc * nrows, tw);
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int unit = tid + i * NT;
+      if (unit >= nunits) continue;
+      int iB, rB;
+      pair_of(unit, iB, rB);
+      const int iA = unit;
+      const bool zero_bin = (k1 == 0 && iA == 0);
+      const bool self = (rB == 0 && iB == iA);
+      // spectra of the chunk's real inputs at bins A and B (in place: the two
+      // positions of a bin pair belong to this thread alone)
+      for (int c = 0; c < nc; ++c) {
+        const cplx<T> ZA = X[(c * nrows) * STR + lds_pad(iA)];
+        const cplx<T> ZB = X[(c * nrows + rB) * STR + lds_pad(iB)];
+        cplx<T> xa, xb;
+        if (zero_bin) {
+          xa = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
+          xb = cplx<T>{ZA.re - ZA.im, Real<T>::zero()};
+        } else {
+          const cplx<T> zc = cconj(ZB);
+          const cplx<T> E = cplx<T>{half_of(ZA.re + zc.re), half_of(ZA.im + zc.im)};
+          const cplx<T> dd = csub(ZA, zc);
+          const cplx<T> t = cmul(wk[i], cplx<T>{half_of(dd.im), half_of(-dd.re)});
+          xa = cadd(E, t);
+          xb = self ? xa : cconj(csub(E, t));
+        }
+        X[(c * nrows) * STR + lds_pad(iA)] = cnorm(xa);
+        if (zero_bin) nyq[c] = cnorm(xb);
+        else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
+      }
+      cplx<T> PA = czero<T>(), PB = czero<T>();
+      for (int t = t0; t < t1; ++t) {
+        const int oe = poff[t + 1];
+        int o = pfrom[t];
+        bool fresh = o == poff[t];
+        for (; o < oe; ++o) {
+          const int c = pids[o];
+          const cplx<T> fa = X[(c * nrows) * STR + lds_pad(iA)];
+          const cplx<T> fb = zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)];
+          PA = fresh ? fa : cmul(PA, fa);
+          PB = fresh ? fb : cmul(PB, fb);
+          fresh = false;
+        }
+        const T cf = Real<T>::from_d(pcoef[t]);
+        YA[i] = cnorm(cadd(YA[i], cscale(PA, cf)));
+        YB[i] = cnorm(cadd(YB[i], cscale(PB, cf)));
+      }
+    }
+  }
+  lds_barrier();   // every chunk's reads of X are done: rows 0-1 take the packed sum
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) {
+    const int unit = tid + i * NT;
+    if (unit >= nunits) continue;
+    int iB, rB;
+    pair_of(unit, iB, rB);
+    const int iA = unit;
+    const cplx<T> A = YA[i], B = YB[i];
+    if (k1 == 0 && iA == 0) {
+      X[0] = cnorm(cplx<T>{A.re + B.re, A.re - B.re});
+    } else {
+      const cplx<T> s = cadd(A, cconj(B)), df = csub(A, cconj(B));
+      X[lds_pad(iA)] = cnorm(cadd(s, cmul_i(cmulc(df, wk[i]))));
+      if (!(rB == 0 && iB == iA)) X[rB * STR + lds_pad(iB)] = cnorm(cadd(cconj(s), cmul_i(cmul(wk[i], cconj(df)))));
+    }
+  }
+  lds_barrier();
+  fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T>::value>(X, nrows, tw);
+
+  cplx<T>* V = (cplx<T>*)sd.V;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int idx = tid + i * NT;
+    if (idx < nrows * M2) {
+      const int rr = idx / M2, j2 = idx - rr * M2;
+      const int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) & (a.L - 1);
+      stg(V + ((int64_t)row_of(rr) * M2 + j2), cnorm(cmulc(X[rr * STR + lds_pad(j2)], twL<T>(a, e))));
+    }
+  }
+
+  // loss-term weights G_c (as in row_kernel), tables read from device memory
+  if (k1 == 0) {
+    for (int c = tid; c < u; c += NT) {
+      double t = 0.0;
+      for (int wv = 0; wv < NWAVE; ++wv) t += red[wv * a.umax + c];
+      sdot[c] = t;
+    }
+    lds_barrier();
+    const int* qoff = sd.tab + sd.o_qoff;
+    const int* qids = sd.tab + sd.o_qids;
+    const int* qkm = sd.tab + sd.o_qkm;
+    for (int c = tid; c < u; c += NT) {
+      double Gc = 0.0;
+      for (int t = 0; t < sd.Tq; ++t) {
+        if (ldg(qkm + t) != c) continue;
+        double pr = ldg(sd.coef + (sd.Tp + t));
+        for (int o = ldg(qoff + t); o < ldg(qoff + t + 1); ++o) pr *= sdot[ldg(qids + o)];
+        Gc += pr;
+      }
+      stg(sd.G + c, Gc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Elementwise Heun stages of the unfused (term-by-term) evaluation:
 //   stage 1: n~ = n + dt k1        stage 2: n = n + dt/2 (k1 + k2)
 // ---------------------------------------------------------------------------
@@ -851,6 +1051,12 @@ size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max) {
          (size_t)coef_max * 8 + (size_t)(2 * kThreads / 64 + 1) * umax * 8 + (size_t)tab_max * 4 + 16;
 }
 
+size_t row_chunk_smem_bytes(int prec, int cmax, int umax, int M2, int, int) {
+  size_t cs = prec == 1 ? 8 : 16;
+  return (size_t)(M2 <= 512 ? M2 : 0) * cs + (size_t)cmax * 2 * lds_len(M2) * cs + (size_t)cmax * cs +
+         (size_t)(2 * kThreads / 64 + 1) * umax * 8 + 16;
+}
+
 int col_batch(int prec, int M1, int u, int nworkgroups) {
   size_t cs = prec == 1 ? 8 : 16;
   size_t gmax = 1024 / M1 > 0 ? 1024 / M1 : 1;
@@ -872,6 +1078,20 @@ template <class T, int M2>
 static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s) {
   // saturating launches trade registers for several resident work groups per CU;
   // smaller ones keep every register (no spills) for the shortest chains
+  if (a.cmax > 0) {
+    const size_t smem = row_chunk_smem_bytes(sizeof(cplx<T>) == 8 ? 1 : 0, a.cmax, a.umax, a.M2, 0, 0);
+    static bool chunk_attr = false;
+    if (!chunk_attr) {
+      hipError_t e = hipFuncSetAttribute((const void*)row_chunk_kernel<T, M2>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+      if (e != hipSuccess) return e;
+      chunk_attr = true;
+    }
+    if (smem > 160 * 1024 - 4096) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((row_chunk_kernel<T, M2>), dim3(a.nslots * (a.M1 / 2 + 1)),
+                       dim3(RowThreads<M2, false>::value), smem, s, a);
+    return hipGetLastError();
+  }
   constexpr bool kHasLean = M2 <= 512;
   const bool lean = kHasLean && (int64_t)a.nslots * (a.M1 / 2 + 1) >= kLeanWorkgroups;
   const size_t smem = row_smem_bytes(sizeof(cplx<T>) == 8 ? 1 : 0, a.umax, a.M2, a.tab_max, a.coef_max);

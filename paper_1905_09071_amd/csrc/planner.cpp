@@ -8,12 +8,17 @@
 //    sorted ids of the other modes), merged with integer multiplicities;
 //  - two-pass split M = M1*M2 of the half-length complex transform with the
 //    row working set u*2*M2 complex values capped at 64 KiB while M1 <= 2048;
-//  - column tile g = min(M2, max(1, 1024/M1)).
+//  - column tile g = min(M2, max(1, 1024/M1));
+//  - when the row working set still exceeds 144 KiB, the row pass combines the
+//    gain terms chunk by chunk: terms visited by their ascending distinct ids
+//    (ties in gain-term order), a chunk growing while the union of its ids
+//    stays within 148 KiB / (2*(M2 + M2/16)*cs) columns.
 #include "planner.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <tuple>
 
@@ -120,13 +125,39 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   int64_t M1 = int64_t(1) << ((lg + 1) / 2);
   int64_t M2 = P.M / M1;
   while ((int64_t)P.u * 2 * M2 * cs > 65536 && M1 < 2048) { M1 *= 2; M2 /= 2; }
-  if (M1 > 2048 || (int64_t)P.u * 2 * M2 * cs > 147456) {
-    *err = "too many distinct factor columns for the two-pass transform at this length";
-    return AGG_EUNSUPPORTED;
-  }
+  if (M1 > 2048) { *err = "no two-pass split at this length"; return AGG_EUNSUPPORTED; }
   P.M1 = (int)M1; P.M2 = (int)M2;
   P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1));
   P.b = (ilog2(L) + 1) / 2;
+
+  if ((int64_t)P.u * 2 * M2 * cs > 147456) {
+    // chunk capacity: 148 KiB of rows at the row pass's padded LDS length
+    P.cmax = (int)(151552 / (2 * (M2 + M2 / 16) * cs));
+    std::vector<std::pair<std::vector<int>, int>> order;   // (distinct ids, term)
+    for (size_t t = 0; t < P.p_ids.size(); ++t) {
+      std::vector<int> s = P.p_ids[t];                     // already ascending
+      s.erase(std::unique(s.begin(), s.end()), s.end());
+      if ((int)s.size() > P.cmax) {
+        *err = "a gain term has more distinct factor columns than the row pass holds at this length";
+        return AGG_EUNSUPPORTED;
+      }
+      order.push_back({s, (int)t});
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<int> cols, terms;
+    for (auto& e : order) {
+      std::vector<int> un;
+      std::set_union(cols.begin(), cols.end(), e.first.begin(), e.first.end(), std::back_inserter(un));
+      if (!terms.empty() && (int)un.size() > P.cmax) {
+        P.ch_cols.push_back(cols); P.ch_terms.push_back(terms);
+        terms.clear();
+        un = e.first;
+      }
+      cols = un;
+      terms.push_back(e.second);
+    }
+    if (!terms.empty()) { P.ch_cols.push_back(cols); P.ch_terms.push_back(terms); }
+  }
 
   P.flat = {L, M1, M2, P.g, P.u, (int64_t)P.p_ids.size(), (int64_t)P.q_ids.size(), De};
   for (int id : P.colmap) P.flat.push_back(id);
@@ -140,6 +171,13 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
     P.flat.push_back(P.q_mult[t]);
     P.flat.push_back(P.q_kmode[t]);
     for (int id : P.q_ids[t]) P.flat.push_back(id);
+  }
+  P.flat.push_back((int64_t)P.ch_cols.size());
+  for (size_t c = 0; c < P.ch_cols.size(); ++c) {
+    P.flat.push_back((int64_t)P.ch_cols[c].size());
+    P.flat.push_back((int64_t)P.ch_terms[c].size());
+    for (int id : P.ch_cols[c]) P.flat.push_back(id);
+    for (int t : P.ch_terms[c]) P.flat.push_back(t);
   }
   return AGG_OK;
 }

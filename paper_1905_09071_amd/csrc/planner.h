@@ -25,6 +25,10 @@ struct PlanTables {
   // loss terms: k-mode id, other ids (sorted), multiplicity; coef = mult/(d-1)!
   std::vector<int> q_d, q_kmode, q_mult;
   std::vector<std::vector<int>> q_ids;
+  // row-pass chunks when the combine cannot hold every column at once (cmax > 0):
+  // each chunk's distinct column ids (ascending) and gain-term indices
+  int cmax = 0;
+  std::vector<std::vector<int>> ch_cols, ch_terms;
   std::vector<int64_t> flat;
 };
 

@@ -3,6 +3,7 @@ include/agg.h, its host planner reproduces the oracle's written plan rules bit
 for bit, its binary64 twiddles are within 1 ulp of the correctly rounded
 values, and invalid arguments are refused before any device call."""
 import ctypes
+import math
 import os
 import re
 
@@ -153,3 +154,105 @@ def test_null_plan_calls_are_refused():
     assert L.agg_plan_destroy(None) == agg.AGG_OK
     assert L.agg_poll(None, 1, None, None) == agg.AGG_EINVAL
     assert L.agg_engine_destroy(None) == agg.AGG_OK
+
+
+# ---- row-pass chunks and host kernel compression --------------------------------
+
+def _expsum_kernel(D, N, R=31):
+    f = synth.sum_kernel_values(2, D * N)
+    alpha, w, err = agg.expsum_fit(f, 2, R)
+    return synth.kernel_expsum(D, N, alpha, w), err / f.max()
+
+
+@pytest.mark.parametrize("D,N,prec", [(5, 65536, "fp64"), (5, 65536, "fp32"), (5, 1 << 20, "fp32c"),
+                                      (5, 1 << 20, "fp32")])
+def test_chunked_plan_tables_bit_exact(D, N, prec):
+    """The chunk rule on the compressed (sum_m i_m)^(1/2) kernel (64 distinct
+    columns, two per rank-one term)."""
+    k, _ = _expsum_kernel(D, N)
+    kk = {d: np.asarray(v) for d, v in k.items()}
+    ref = oracle_plan(D, N, kk, prec)
+    got = agg.plan_tables(D, N, k, prec)
+    assert np.array_equal(got, ref["flat"])
+    M2, cs = ref["M2"], 8 if prec == "fp32" else 16
+    if ref["u"] * 2 * M2 * cs > 147456:
+        assert len(ref["chunks"]) >= 2
+        for cols, terms in ref["chunks"]:
+            assert len(cols) <= 151552 // (2 * (M2 + M2 // 16) * cs)
+    else:
+        assert ref["chunks"] == []
+
+
+def test_chunked_plan_tables_random_kernel():
+    """Chunks of a kernel without shared columns (terms of 2, 3 and 4 columns)."""
+    D, N = 4, 65536
+    k = synth.kernel_random(D, N, {2: 4, 3: 8, 4: 11}, 21)
+    ref = oracle_plan(D, N, k, "fp64")
+    assert ref["u"] == 76 and len(ref["chunks"]) == 2
+    assert np.array_equal(agg.plan_tables(D, N, k, "fp64"), ref["flat"])
+    covered = sorted(t for _, terms in ref["chunks"] for t in terms)
+    assert covered == list(range(len(ref["pterms"])))
+
+
+def test_expsum_fit_rank32_sqrt_sum_kernel():
+    """(i_1+..+i_5)^(1/2) for N = 2^20: rank 32 (31 exponentials and a constant)
+    within 1e-8 of max C over every reachable total size, the reported error
+    being the true maximum (re-evaluated here independently)."""
+    D, N = 5, 1 << 20
+    f = synth.sum_kernel_values(2, D * N)
+    alpha, w, err = agg.expsum_fit(f, 2, 31)
+    assert alpha.size == 31 and w.size == 32 and np.all(alpha > 0) and np.all(np.diff(alpha) > 0)
+    assert err <= 1e-8 * f.max()
+    s = np.arange(2, D * N + 1, dtype=np.float64)
+    worst = 0.0
+    for i0 in range(0, s.size, 1 << 18):
+        ss = s[i0:i0 + (1 << 18)]
+        v = w[0] + np.exp(-np.outer(ss, alpha)) @ w[1:]
+        worst = max(worst, float(np.max(np.abs(v - f[i0:i0 + (1 << 18)]))))
+    assert abs(worst - err) <= 1e-6 * err
+    # the factors reproduce the function of the total size at sampled multi-indices
+    k = synth.kernel_expsum(D, 4096, alpha, w)
+    rng = np.random.default_rng(5)
+    for d in (2, 5):
+        U = k[d]
+        for _ in range(20):
+            idx = rng.integers(1, 4097, size=d)
+            c = sum(np.prod([U[m][r, idx[m] - 1] for m in range(d)]) for r in range(32))
+            assert abs(c - math.sqrt(idx.sum())) <= err + 1e-12 * np.abs(w).sum()
+
+
+def test_expsum_fit_special_cases_and_errors():
+    f = np.full(1000, 2.5)
+    alpha, w, err = agg.expsum_fit(f, 1, 0)
+    assert alpha.size == 0 and w[0] == pytest.approx(2.5, abs=1e-12) and err <= 1e-12
+    # 1/s (completely monotone) converges geometrically in the number of terms
+    s = np.arange(1, 10001, dtype=np.float64)
+    errs = [agg.expsum_fit(1.0 / s, 1, R)[2] for R in (8, 16, 24)]
+    assert errs[1] <= 0.1 * errs[0] and errs[2] <= 0.1 * errs[1] and errs[2] <= 1e-7
+    with pytest.raises(agg.AggError) as e:
+        agg.expsum_fit(f, 0, 4)
+    assert e.value.status == agg.AGG_EINVAL
+    with pytest.raises(agg.AggError) as e:
+        agg.expsum_fit(f, 1, 65)
+    assert e.value.status == agg.AGG_EINVAL
+    g = f.copy()
+    g[7] = np.nan
+    with pytest.raises(agg.AggError) as e:
+        agg.expsum_fit(g, 1, 4)
+    assert e.value.status == agg.AGG_ENONFINITE
+
+
+def test_expsum_fit_relative_error():
+    """A relative fit bounds |fit - f| / |f| at every integer (checked here at
+    all of them), and is refused for a vanishing f."""
+    s = np.arange(2, 200001, dtype=np.float64)
+    f = np.sqrt(s)
+    alpha, w, err = agg.expsum_fit(f, 2, 24, relative=True)
+    v = w[0] + np.exp(-np.outer(s, alpha)) @ w[1:]
+    worst = float(np.max(np.abs(v - f) / f))
+    assert abs(worst - err) <= 1e-6 * err and err <= 1e-7
+    _, _, aerr = agg.expsum_fit(f, 2, 24)
+    assert aerr / f.max() <= err      # the absolute fit is tighter relative to max f
+    with pytest.raises(agg.AggError) as e:
+        agg.expsum_fit(np.zeros(10), 1, 2, relative=True)
+    assert e.value.status == agg.AGG_EINVAL

@@ -1,0 +1,151 @@
+"""GPU parity of the chunked row pass: kernel sets whose distinct factor columns
+do not all fit in a row-pass workgroup's LDS at once (the planner's chunk rule).
+
+Cases:
+  * a random kernel without shared columns, D = 4, N = 65536 (u = 76, two
+    chunks), against the oracle's per-rank FFT evaluation of the CP sums;
+  * the non-separable kernel C^(d) = (i_1 + ... + i_d)^(1/2), compressed on the
+    host to CP rank 32 per order (31 exponentials and a constant, one fit shared
+    by every order), D = 5: at N = 65536 against the per-rank FFT evaluation,
+    and at the full N = 2^20 (transform length 2^23, 64 distinct columns in
+    chunks of two) on a batch of states with short support, where the oracle's
+    per-rank direct convolutions are exact and cheap; one Heun step too.
+
+Tolerances.  The exponential-sum weights alternate in sign and exceed the
+kernel's values, so the spectral path rounds terms larger than their sum: the
+rounding bound of each precision is scaled by the amplification
+A = max_s sum_r |w_r exp(-alpha_r s)| / max_s |f(s)| (at least 1).  The error
+of the compressed kernel itself (the fit) is reported against the exact
+function through the function-of-sum identity, not asserted."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+agg = pytest.importorskip("paper_1905_09071_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"fp64": 1e-12, "fp32c": 1e-10, "fp32": 1e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gpu_rhs(D, N, kernel, n, prec, batch=1):
+    plan = agg.Plan(D, N, kernel, prec=prec, batch=batch)
+    nt = torch.tensor(np.asarray(n).reshape(-1), dtype=torch.float64, device=DEV)
+    out = plan.rhs(nt)
+    torch.cuda.synchronize()
+    r = out.cpu().numpy().reshape(batch, N) if batch > 1 else out.cpu().numpy()
+    plan.close()
+    return r
+
+
+def dense(kernel):
+    return {d: np.asarray(v) for d, v in kernel.items()}
+
+
+def rhs_short(D, N, kernel, v, kmax):
+    """Oracle RHS of a state whose support lies in [1, kmax/D]: the gain term
+    vanishes beyond kmax, so only its first kmax outputs are formed."""
+    nz = np.nonzero(v)[0]
+    assert nz.size == 0 or (nz[-1] + 1) * D <= kmax
+    p, q = oracle.rhs_conv(D, N, kernel, v, kmax=kmax)
+    p[:, kmax:] = 0.0
+    return oracle.total_rhs(p, q)
+
+
+def expsum(D, N, R=31):
+    f = synth.sum_kernel_values(2, D * N)
+    alpha, w, err = agg.expsum_fit(f, 2, R)
+    s = np.arange(2, D * N + 1, dtype=np.float64)
+    amp = 0.0
+    for i0 in range(0, s.size, 1 << 18):
+        amp = max(amp, float(np.max(np.exp(-np.outer(s[i0:i0 + (1 << 18)], alpha)) @ np.abs(w[1:]) + abs(w[0]))))
+    return synth.kernel_expsum(D, N, alpha, w), alpha, w, err / f.max(), max(1.0, amp / f.max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_chunked_random_kernel(prec):
+    D, N = 4, 65536
+    k = synth.kernel_random(D, N, {2: 4, 3: 8, 4: 11}, 21)
+    tab = oracle.plan_tables(D, N, k, prec)
+    say(f"[chunked random] D={D} N={N} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
+    n = synth.n0_random_dense(N, 22, decay=1e-4)
+    f = gpu_rhs(D, N, k, n, prec)
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, k, n))
+    e = rel(f, ref)
+    say(f"  rhs err {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def sum65536():
+    D, N = 5, 65536
+    k, alpha, w, fit_err, amp = expsum(D, N)
+    n = synth.n0_random_dense(N, 31, decay=2e-4)
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, dense(k), n))
+    exact = oracle.total_rhs(*oracle.rhs_sum_kernel(D, N, np.sqrt(np.arange(D * N + 1.0)), n))
+    return dict(D=D, N=N, k=k, n=n, ref=ref, exact=exact, fit_err=fit_err, amp=amp)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_chunked_sum_kernel_n65536(sum65536, prec):
+    c = sum65536
+    tab = oracle.plan_tables(c["D"], c["N"], dense(c["k"]), prec)
+    say(f"[sum kernel] D={c['D']} N={c['N']} u={tab['u']} chunks={len(tab['chunks'])} prec={prec} "
+        f"fit err {c['fit_err']:.2e} amplification {c['amp']:.1f}")
+    f = gpu_rhs(c["D"], c["N"], c["k"], c["n"], prec)
+    e = rel(f, c["ref"])
+    say(f"  rhs err vs CP oracle {e:.3e}; vs the exact kernel {rel(f, c['exact']):.3e}")
+    assert e <= TOL[prec] * c["amp"]
+
+
+@pytest.fixture(scope="module")
+def sum_full():
+    D, N, B = 5, 1 << 20, 4
+    k, alpha, w, fit_err, amp = expsum(D, N)
+    n0 = np.stack([synth.n0_uniform_head(N, s, 16) for s in range(B)])
+    return dict(D=D, N=N, B=B, k=k, kd=dense(k), n0=n0, fit_err=fit_err, amp=amp)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_chunked_sum_kernel_full_size_batch(sum_full, prec):
+    c = sum_full
+    D, N, B = c["D"], c["N"], c["B"]
+    tab = oracle.plan_tables(D, N, c["kd"], prec)
+    say(f"[sum kernel full] D={D} N={N} B={B} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
+    plan = agg.Plan(D, N, c["k"], prec=prec, batch=B)
+    n = torch.tensor(c["n0"].reshape(-1), device=DEV)
+    f = plan.rhs(n)
+    torch.cuda.synchronize()
+    f = f.cpu().numpy().reshape(B, N)
+    fv = np.sqrt(np.arange(D * 16 * D + 1.0))   # f(s) for s <= D * (16 D)
+    for b in (0, B - 1):
+        ref = rhs_short(D, N, c["kd"], c["n0"][b], 100)
+        e = rel(f[b], ref)
+        pe, qe = oracle.rhs_sum_kernel(D, 16 * D, fv, c["n0"][b][:16 * D])
+        ex = oracle.total_rhs(pe, qe)
+        say(f"  member {b}: rhs err {e:.3e}; vs the exact kernel {rel(f[b, :16 * D], ex):.3e}")
+        assert e <= TOL[prec] * c["amp"]
+    h = 1e-4
+    plan.rk2_step(n, h)
+    torch.cuda.synchronize()
+    nb = n.cpu().numpy().reshape(B, N)
+    # stage 1 spreads the support to [1, 80], stage 2's gain reaches 400
+    ref = oracle.heun_solve(lambda v: rhs_short(D, N, c["kd"], v, 400), c["n0"][0], h, h)
+    e = rel(nb[0], ref)
+    say(f"  heun member 0: err {e:.3e}")
+    assert e <= TOL[prec] * c["amp"]
+    plan.close()
