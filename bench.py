@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--serving", type=int, default=512, help="requests in the serving sample (0 = skip)")
     ap.add_argument("--batch", type=int, default=64, help="states of the batched C3 line (0 = skip)")
     ap.add_argument("--c5", type=int, default=1, help="run the D=5 N=2^20 batch-64 line (0 = skip)")
+    ap.add_argument("--c5b", type=int, default=64,
+                    help="states of the D=5 N=2^20 compressed (sum i)^(1/2) line (0 = skip)")
     ap.add_argument("--quick", action="store_true",
                     help="profiling aid: time only the primary precision (on --batch states if > 0), "
                          "no pass timing, no other lines")
@@ -275,6 +277,38 @@ def main():
             del n
             torch.cuda.empty_cache()
 
+    c5b = None
+    if args.c5b:
+        # (i_1+..+i_d)^(1/2), compressed on the host to rank 32 per order (not timed)
+        D5, N5, B = 5, 1 << 20, args.c5b
+        fv = synth.sum_kernel_values(2, D5 * N5)
+        t0 = time.perf_counter()
+        alpha, w, ferr = agg.expsum_fit(fv, 2, 31)
+        tfit = time.perf_counter() - t0
+        k5 = synth.kernel_expsum(D5, N5, alpha, w, weighted=True)   # 32 columns shared by all orders
+        n0 = np.stack([synth.n0_uniform_head(N5, s, 16) for s in range(B)])
+        c5b = {"batch": B, "rank_per_order": 32, "distinct_columns": 32,
+               "fit_max_err_over_max_C": float(f"{ferr / fv.max():.3e}"), "fit_seconds": round(tfit, 2)}
+        for prec in ("fp64", "fp32c"):
+            plan = agg.Plan(D5, N5, k5, prec, batch=B)
+            n = torch.tensor(n0.reshape(-1), dtype=torch.float64, device="cuda:0")
+            h, s5 = 1e-4, 3
+            plan.solve(n, h, h, stats=False)      # one untimed step
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.solve(n, h, s5 * h, stats=False)
+            e1.record()
+            torch.cuda.synchronize()
+            t5 = e0.elapsed_time(e1) / 1000.0
+            c5b[prec] = round(2 * s5 * B / t5, 2)
+            log(f"[bench] D=5 N=2^20 sqrt-sum kernel (rank 32, u=32) batch {B} {prec}: {s5} steps in "
+                f"{t5*1e3:.1f} ms -> {c5b[prec]} RHS/s")
+            plan.close()
+            del n
+            torch.cuda.empty_cache()
+
     prim = results[args.prec]
     cs = PREC_BYTES[args.prec]
     # dominant kernel of a time step: the pass with the largest device time
@@ -321,6 +355,7 @@ def main():
         "plain_fp64_rhs_per_s": round(plain_rate, 2),
         "batched_rhs_per_s": {"batch": args.batch, **batched} if batched else None,
         "d5_n2e20_batch64_rhs_per_s": c5 or None,
+        "d5_n2e20_sqrt_sum_kernel_rhs_per_s": c5b,
         "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,

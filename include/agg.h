@@ -61,14 +61,19 @@ enum {
 typedef enum { AGG_FP64 = 0, AGG_FP32 = 1, AGG_FP32C = 2 } agg_precision;
 #define AGG_PLAIN 0x100
 
-/* One collision order d: C^(d) = sum_r prod_m U_m(i_m, r).
+/* One collision order d: C^(d) = sum_r weight[r] prod_m U_m(i_m, r).
  * U[m-1] is a HOST pointer to N*rank doubles, column-major by rank:
  * U[m-1][r*N + (i-1)] = U^(d)_m(i, r), for m = 1..d.  Mode m = d is the k-mode.
+ * weight is a HOST pointer to rank doubles, or NULL for all ones: the CP form
+ * of Sec. 1 has no weights, and a weight is only a scalar factor of rank-one
+ * term r, carried into that term's coefficient, so that factor columns equal
+ * up to a scale can be given (and shared) as one column.
  * rank = 0 means the order is absent.  Entries U[d..AGG_MAX_D-1] are ignored. */
 typedef struct {
   int32_t d;
   int32_t rank;
   const double* U[AGG_MAX_D];
+  const double* weight;
 } agg_term;
 
 typedef struct agg_plan agg_plan;
@@ -158,9 +163,9 @@ agg_status agg_twiddles(int64_t P, double* out);
  * (Sec. 2, remark on the canonical format); this class has one through a 1-D
  * exponential sum, because exp(-a (i_1+..+i_d)) = prod_m exp(-a i_m):
  *     f(s) ~ w[0] + sum_{r=1..R} w[r] exp(-alpha[r-1] s),
- * and order d then has CP rank R+1 with, for term r, the column
- * w[r] exp(-alpha[r-1] i) in mode 1 and exp(-alpha[r-1] i) in modes 2..d
- * (term 0: the constant w[0] in mode 1, ones elsewhere).  One fit over
+ * and order d then has CP rank R+1: term r has weight w[r] and the column
+ * exp(-alpha[r-1] i) in every mode (term 0: ones), so that the R+1 columns are
+ * shared by every mode and order.  One fit over
  * [2, D N] serves every order d <= D; the kernel error of order d is the fit
  * error over [d, d N].
  *   f       host, f[s - smin] = f(s) for every integer s in [smin, smax]

@@ -19,13 +19,17 @@ __all__ = ["Plan", "Engine", "plan_tables", "twiddles", "expsum_fit", "AggError"
 
 
 def make_terms(D: int, N: int, kernel: dict):
-    """Build the agg_term array; returns (array, keepalive list).  The factors
-    of order d are an array of shape (d, R, N), or a list of d arrays of shape
-    (R, N) (modes may then share one array)."""
+    """Build the agg_term array; returns (array, count, keepalive list).  The
+    factors of order d are an array of shape (d, R, N), or a list of d arrays
+    of shape (R, N) (modes may then share one array), or a dict with those
+    factors under "U" and R per-rank weights under "weight"."""
     items = sorted(kernel.items())
     arr = (agg_term * max(len(items), 1))()
     keep = []
     for t, (d, U) in enumerate(items):
+        weight = None
+        if isinstance(U, dict):
+            weight, U = U.get("weight"), U["U"]
         modes = list(U) if isinstance(U, (list, tuple)) else None
         if modes is None:
             U = np.asarray(U, dtype=np.float64)
@@ -41,6 +45,12 @@ def make_terms(D: int, N: int, kernel: dict):
             col = np.ascontiguousarray(modes[m], dtype=np.float64)
             keep.append(col)
             arr[t].U[m] = col.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if weight is not None:
+            wv = np.ascontiguousarray(weight, dtype=np.float64)
+            if wv.shape != (arr[t].rank,):
+                raise ValueError(f"order {d}: one weight per rank expected")
+            keep.append(wv)
+            arr[t].weight = wv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return arr, len(items), keep
 
 

@@ -21,7 +21,7 @@ DP = ctypes.POINTER(ctypes.c_double)
 
 
 class agg_term(ctypes.Structure):
-    _fields_ = [("d", ctypes.c_int32), ("rank", ctypes.c_int32), ("U", DP * AGG_MAX_D)]
+    _fields_ = [("d", ctypes.c_int32), ("rank", ctypes.c_int32), ("U", DP * AGG_MAX_D), ("weight", DP)]
 
 
 class agg_solve_stats(ctypes.Structure):

@@ -122,7 +122,7 @@ SharedImage make_shared_image(const PlanTables& T) {
     const int t = torder[i];
     for (int id : tids[i]) p_ids.push_back(id);
     p_off.push_back((int)p_ids.size());
-    coef.push_back((double)T.p_mult[t] / factorial((int)T.p_ids[t].size()));
+    coef.push_back(T.p_wsum[t] / factorial((int)T.p_ids[t].size()));
     // a term whose ids start with all of the previous term's ids continues
     // that term's running product (same-order multiplications, fewer of them)
     int from = p_off[i];
@@ -137,7 +137,7 @@ SharedImage make_shared_image(const PlanTables& T) {
     for (int id : T.q_ids[t]) q_ids.push_back(id);
     q_off.push_back((int)q_ids.size());
     q_km.push_back(T.q_kmode[t]);
-    coef.push_back((double)T.q_mult[t] / factorial(T.q_d[t] - 1));
+    coef.push_back(T.q_wsum[t] / factorial(T.q_d[t] - 1));
   }
   std::vector<int> blob;
   auto put = [&](const std::vector<int>& v) {
@@ -399,6 +399,7 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
       one.d = terms[t].d;
       one.rank = 1;
       for (int m = 0; m < one.d; ++m) one.U[m] = terms[t].U[m] + (size_t)r * N;
+      one.weight = terms[t].weight ? terms[t].weight + r : nullptr;
       agg_plan* sub = nullptr;
       rc = plan_create_impl(D, N, &one, 1, prec, batch, hip_stream, false, &sub);
       if (rc == AGG_OK) p->subs.push_back(sub);

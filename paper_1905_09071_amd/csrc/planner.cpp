@@ -5,7 +5,8 @@
 //    wrapped tail lands on it, and one inverse transform serves every d;
 //  - column ids by first appearance in scan order d, m, r, bitwise equality;
 //  - gain terms keyed by the sorted id multiset, loss terms by (d, k-mode id,
-//    sorted ids of the other modes), merged with integer multiplicities;
+//    sorted ids of the other modes), merged with integer multiplicities (and
+//    the sums of the merged ranks' weights, in scan order);
 //  - two-pass split M = M1*M2 of the half-length complex transform with the
 //    row working set u*2*M2 complex values capped at 64 KiB while M1 <= 2048;
 //  - column tile g = min(M2, max(1, 1024/M1));
@@ -60,6 +61,9 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
     for (int m = 0; m < d; ++m)
       for (int64_t i = 0; i < (int64_t)byd[d]->rank * N; ++i)
         if (!std::isfinite(byd[d]->U[m][i])) { *err = "non-finite kernel factor"; return AGG_ENONFINITE; }
+    if (byd[d]->weight)
+      for (int r = 0; r < byd[d]->rank; ++r)
+        if (!std::isfinite(byd[d]->weight[r])) { *err = "non-finite kernel weight"; return AGG_ENONFINITE; }
   }
 
   PlanTables& P = *out;
@@ -91,32 +95,39 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   for (int c = 0; c < P.u; ++c) P.ucols[c].assign(uptr[c], uptr[c] + N);
 
   // gain and loss terms
-  std::map<std::vector<int>, int> pt;                          // key: sorted ids
-  std::map<std::tuple<int, int, std::vector<int>>, int> qt;    // (d, kmode, others)
+  using Acc = std::pair<int, double>;                          // (multiplicity, weight sum)
+  std::map<std::vector<int>, Acc> pt;                          // key: sorted ids
+  std::map<std::tuple<int, int, std::vector<int>>, Acc> qt;    // (d, kmode, others)
   for (int d = 2; d <= D; ++d) {
     int R = byd[d] ? byd[d]->rank : 0;
     for (int r = 0; r < R; ++r) {
+      const double wr = byd[d]->weight ? byd[d]->weight[r] : 1.0;
       std::vector<int> ids;
       for (int m = 0; m < d; ++m) ids.push_back(cmap[std::make_tuple(d, m, r)]);
       std::vector<int> s = ids;
       std::sort(s.begin(), s.end());
-      pt[s] += 1;
+      Acc& a = pt[s];
+      a.first += 1; a.second += wr;
       std::vector<int> o(ids.begin(), ids.end() - 1);
       std::sort(o.begin(), o.end());
-      qt[std::make_tuple(d, ids[d - 1], o)] += 1;
+      Acc& b = qt[std::make_tuple(d, ids[d - 1], o)];
+      b.first += 1; b.second += wr;
     }
   }
-  std::vector<std::pair<std::vector<int>, int>> pv(pt.begin(), pt.end());
+  std::vector<std::pair<std::vector<int>, Acc>> pv(pt.begin(), pt.end());
   std::stable_sort(pv.begin(), pv.end(), [](const auto& a, const auto& b) {
     if (a.first.size() != b.first.size()) return a.first.size() < b.first.size();
     return a.first < b.first;
   });
-  for (auto& kv : pv) { P.p_ids.push_back(kv.first); P.p_mult.push_back(kv.second); }
+  for (auto& kv : pv) {
+    P.p_ids.push_back(kv.first); P.p_mult.push_back(kv.second.first); P.p_wsum.push_back(kv.second.second);
+  }
   for (auto& kv : qt) {   // std::map orders by (d, kmode, others) already
     P.q_d.push_back(std::get<0>(kv.first));
     P.q_kmode.push_back(std::get<1>(kv.first));
     P.q_ids.push_back(std::get<2>(kv.first));
-    P.q_mult.push_back(kv.second);
+    P.q_mult.push_back(kv.second.first);
+    P.q_wsum.push_back(kv.second.second);
   }
 
   // two-pass split

@@ -19,11 +19,15 @@ struct PlanTables {
   int u = 0;                               // distinct factor columns
   std::vector<int> colmap;                 // id per (d, m, r) in scan order
   std::vector<std::vector<double>> ucols;  // u columns of N doubles
-  // gain terms: column ids (sorted), multiplicity; coefficient = mult / d!
+  // gain terms: column ids (sorted), multiplicity, sum of the merged ranks'
+  // weights (= multiplicity without weights); coefficient = weight sum / d!
   std::vector<std::vector<int>> p_ids;
   std::vector<int> p_mult;
-  // loss terms: k-mode id, other ids (sorted), multiplicity; coef = mult/(d-1)!
+  std::vector<double> p_wsum;
+  // loss terms: k-mode id, other ids (sorted), multiplicity, weight sum;
+  // coefficient = weight sum / (d-1)!
   std::vector<int> q_d, q_kmode, q_mult;
+  std::vector<double> q_wsum;
   std::vector<std::vector<int>> q_ids;
   // row-pass chunks when the combine cannot hold every column at once (cmax > 0):
   // each chunk's distinct column ids (ascending) and gain-term indices

@@ -137,19 +137,21 @@ def sum_kernel_values(smin: int, smax: int, power: float = 0.5) -> np.ndarray:
     return np.arange(smin, smax + 1, dtype=np.float64) ** power
 
 
-def kernel_expsum(D: int, N: int, alpha, w) -> dict:
+def kernel_expsum(D: int, N: int, alpha, w, weighted: bool = False) -> dict:
     """CP factors of C^(d)(i) = w_0 + sum_r w_r exp(-alpha_r (i_1 + ... + i_d)) for
-    every d in [2, D], rank R+1 per order: term 0 has the constant w_0 in mode 1
-    and ones elsewhere, term r has w_r exp(-alpha_r i) in mode 1 and
-    exp(-alpha_r i) in the other modes.  Returned per order as a list of d
-    arrays of shape (R+1, N); the modes share two arrays (W for mode 1, E for
-    the rest) and every order shares the same two."""
+    every d in [2, D], rank R+1 per order, with E[0] = ones and
+    E[r] = exp(-alpha_r i).  Unweighted: term r has w_r E[r] in mode 1 and E[r]
+    in the other modes, returned per order as a list of d arrays of shape
+    (R+1, N) sharing two arrays.  Weighted: every mode of term r is E[r] and
+    the term carries the weight w_r, returned as {"U": [E]*d, "weight": w}."""
     s = sizes(N)
     alpha = np.asarray(alpha, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
     E = np.ones((alpha.size + 1, N), dtype=np.float64)
     for r, a in enumerate(alpha):
         E[r + 1] = np.exp(-a * s)
+    if weighted:
+        return {d: {"U": [E] * d, "weight": w} for d in range(2, D + 1)}
     W = E * w[:, None]
     return {d: [W] + [E] * (d - 1) for d in range(2, D + 1)}
 

@@ -38,3 +38,28 @@ def read_golden_kv(name):
             k, v = line.split()
             out[k] = float(v)
     return out
+
+
+def dense_kernel(kernel):
+    """A kernel dict as the oracle takes it: dense (d, R, N) factor arrays and
+    no weights (a rank's weight multiplies its mode-1 column, which gives the
+    same C^(d) = sum_r w_r prod_m U_m)."""
+    import numpy as np
+    out = {}
+    for d, v in kernel.items():
+        w = None
+        if isinstance(v, dict):
+            w, v = v.get("weight"), v["U"]
+        U = np.array([np.asarray(x, dtype=np.float64) for x in v])
+        if w is not None:
+            U[0] = U[0] * np.asarray(w, dtype=np.float64)[:, None]
+        out[d] = U
+    return out
+
+
+def unweighted_modes(kernel):
+    """The factor arrays of a kernel dict without its weights (what the plan's
+    integer tables depend on)."""
+    import numpy as np
+    return {d: np.array([np.asarray(x, dtype=np.float64) for x in (v["U"] if isinstance(v, dict) else v)])
+            for d, v in kernel.items()}

@@ -13,6 +13,7 @@ import pytest
 import synth
 from oracle.plan import plan_tables as oracle_plan
 from oracle.twiddle import twiddles_ref
+from conftest import unweighted_modes
 
 agg = pytest.importorskip("paper_1905_09071_amd")
 from paper_1905_09071_amd import _lib  # noqa: E402
@@ -158,20 +159,23 @@ def test_null_plan_calls_are_refused():
 
 # ---- row-pass chunks and host kernel compression --------------------------------
 
-def _expsum_kernel(D, N, R=31):
+def _expsum_kernel(D, N, R=31, weighted=False):
     f = synth.sum_kernel_values(2, D * N)
     alpha, w, err = agg.expsum_fit(f, 2, R)
-    return synth.kernel_expsum(D, N, alpha, w), err / f.max()
+    return synth.kernel_expsum(D, N, alpha, w, weighted), err / f.max()
 
 
+@pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("D,N,prec", [(5, 65536, "fp64"), (5, 65536, "fp32"), (5, 1 << 20, "fp32c"),
                                       (5, 1 << 20, "fp32")])
-def test_chunked_plan_tables_bit_exact(D, N, prec):
-    """The chunk rule on the compressed (sum_m i_m)^(1/2) kernel (64 distinct
-    columns, two per rank-one term)."""
-    k, _ = _expsum_kernel(D, N)
-    kk = {d: np.asarray(v) for d, v in k.items()}
+def test_chunked_plan_tables_bit_exact(D, N, prec, weighted):
+    """The chunk rule on the compressed (sum_m i_m)^(1/2) kernel: 64 distinct
+    columns (two per rank-one term) with the weights in mode-1 columns, 32
+    with the weights given as term weights."""
+    k, _ = _expsum_kernel(D, N, weighted=weighted)
+    kk = unweighted_modes(k)
     ref = oracle_plan(D, N, kk, prec)
+    assert ref["u"] == (32 if weighted else 64)
     got = agg.plan_tables(D, N, k, prec)
     assert np.array_equal(got, ref["flat"])
     M2, cs = ref["M2"], 8 if prec == "fp32" else 16
@@ -256,3 +260,15 @@ def test_expsum_fit_relative_error():
     with pytest.raises(agg.AggError) as e:
         agg.expsum_fit(np.zeros(10), 1, 2, relative=True)
     assert e.value.status == agg.AGG_EINVAL
+
+
+def test_term_weights_validation():
+    k = synth.kernel_random(3, 50, 2, 1)
+    kw = {d: {"U": U, "weight": np.array([0.5, -2.0])} for d, U in k.items()}
+    assert np.array_equal(agg.plan_tables(3, 50, kw), agg.plan_tables(3, 50, k))
+    bad = {d: {"U": U, "weight": np.array([0.5, np.inf])} for d, U in k.items()}
+    with pytest.raises(agg.AggError) as e:
+        agg.plan_tables(3, 50, bad)
+    assert e.value.status == agg.AGG_ENONFINITE
+    with pytest.raises(ValueError):
+        agg.plan_tables(3, 50, {2: {"U": k[2], "weight": np.ones(3)}})

@@ -4,12 +4,16 @@ do not all fit in a row-pass workgroup's LDS at once (the planner's chunk rule).
 Cases:
   * a random kernel without shared columns, D = 4, N = 65536 (u = 76, two
     chunks), against the oracle's per-rank FFT evaluation of the CP sums;
+  * per-rank term weights on a small random kernel (the weights folded into
+    mode-1 columns for the oracle);
   * the non-separable kernel C^(d) = (i_1 + ... + i_d)^(1/2), compressed on the
     host to CP rank 32 per order (31 exponentials and a constant, one fit shared
-    by every order), D = 5: at N = 65536 against the per-rank FFT evaluation,
-    and at the full N = 2^20 (transform length 2^23, 64 distinct columns in
-    chunks of two) on a batch of states with short support, where the oracle's
-    per-rank direct convolutions are exact and cheap; one Heun step too.
+    by every order), D = 5, given either with the weights inside the mode-1
+    columns (64 distinct columns) or as term weights (32): at N = 65536 against
+    the per-rank FFT evaluation, and at the full N = 2^20 (transform length
+    2^23, chunks of two columns) on a batch of states with short support,
+    where the oracle's per-rank direct convolutions are exact and cheap; one
+    Heun step too.
 
 Tolerances.  The exponential-sum weights alternate in sign and exceed the
 kernel's values, so the spectral path rounds terms larger than their sum: the
@@ -24,6 +28,7 @@ import pytest
 
 import oracle
 import synth
+from conftest import dense_kernel
 
 torch = pytest.importorskip("torch")
 agg = pytest.importorskip("paper_1905_09071_amd")
@@ -52,10 +57,6 @@ def gpu_rhs(D, N, kernel, n, prec, batch=1):
     return r
 
 
-def dense(kernel):
-    return {d: np.asarray(v) for d, v in kernel.items()}
-
-
 def rhs_short(D, N, kernel, v, kmax):
     """Oracle RHS of a state whose support lies in [1, kmax/D]: the gain term
     vanishes beyond kmax, so only its first kmax outputs are formed."""
@@ -66,14 +67,14 @@ def rhs_short(D, N, kernel, v, kmax):
     return oracle.total_rhs(p, q)
 
 
-def expsum(D, N, R=31):
+def expsum(D, N, R=31, weighted=False):
     f = synth.sum_kernel_values(2, D * N)
     alpha, w, err = agg.expsum_fit(f, 2, R)
     s = np.arange(2, D * N + 1, dtype=np.float64)
     amp = 0.0
     for i0 in range(0, s.size, 1 << 18):
         amp = max(amp, float(np.max(np.exp(-np.outer(s[i0:i0 + (1 << 18)], alpha)) @ np.abs(w[1:]) + abs(w[0]))))
-    return synth.kernel_expsum(D, N, alpha, w), alpha, w, err / f.max(), max(1.0, amp / f.max())
+    return synth.kernel_expsum(D, N, alpha, w, weighted), alpha, w, err / f.max(), max(1.0, amp / f.max())
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
@@ -90,23 +91,40 @@ def test_chunked_random_kernel(prec):
     assert e <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_term_weights(prec):
+    D, N = 4, 40
+    k = synth.kernel_random(D, N, 3, 41)
+    rng = np.random.default_rng(42)
+    kw = {d: {"U": U, "weight": rng.uniform(-2.0, 2.0, size=3)} for d, U in k.items()}
+    n = synth.n0_random_dense(N, 43)
+    f = gpu_rhs(D, N, kw, n, prec)
+    ref = oracle.total_rhs(*oracle.rhs_direct(D, N, dense_kernel(kw), n))
+    e = rel(f, ref)
+    say(f"[weights] D={D} N={N} prec={prec}: rhs err {e:.3e}")
+    assert e <= TOL[prec]
+
+
 @pytest.fixture(scope="module")
 def sum65536():
     D, N = 5, 65536
     k, alpha, w, fit_err, amp = expsum(D, N)
     n = synth.n0_random_dense(N, 31, decay=2e-4)
-    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, dense(k), n))
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, dense_kernel(k), n))
     exact = oracle.total_rhs(*oracle.rhs_sum_kernel(D, N, np.sqrt(np.arange(D * N + 1.0)), n))
-    return dict(D=D, N=N, k=k, n=n, ref=ref, exact=exact, fit_err=fit_err, amp=amp)
+    kw = synth.kernel_expsum(D, N, alpha, w, weighted=True)
+    return dict(D=D, N=N, k=k, kw=kw, n=n, ref=ref, exact=exact, fit_err=fit_err, amp=amp)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
-def test_chunked_sum_kernel_n65536(sum65536, prec):
+def test_chunked_sum_kernel_n65536(sum65536, prec, weighted):
     c = sum65536
-    tab = oracle.plan_tables(c["D"], c["N"], dense(c["k"]), prec)
+    k = c["kw"] if weighted else c["k"]
+    tab = oracle.plan_tables(c["D"], c["N"], {d: np.array(v["U"] if weighted else v) for d, v in k.items()}, prec)
     say(f"[sum kernel] D={c['D']} N={c['N']} u={tab['u']} chunks={len(tab['chunks'])} prec={prec} "
         f"fit err {c['fit_err']:.2e} amplification {c['amp']:.1f}")
-    f = gpu_rhs(c["D"], c["N"], c["k"], c["n"], prec)
+    f = gpu_rhs(c["D"], c["N"], k, c["n"], prec)
     e = rel(f, c["ref"])
     say(f"  rhs err vs CP oracle {e:.3e}; vs the exact kernel {rel(f, c['exact']):.3e}")
     assert e <= TOL[prec] * c["amp"]
@@ -117,16 +135,18 @@ def sum_full():
     D, N, B = 5, 1 << 20, 4
     k, alpha, w, fit_err, amp = expsum(D, N)
     n0 = np.stack([synth.n0_uniform_head(N, s, 16) for s in range(B)])
-    return dict(D=D, N=N, B=B, k=k, kd=dense(k), n0=n0, fit_err=fit_err, amp=amp)
+    kw = synth.kernel_expsum(D, N, alpha, w, weighted=True)
+    return dict(D=D, N=N, B=B, k=k, kw=kw, kd=dense_kernel(k), n0=n0, fit_err=fit_err, amp=amp)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_chunked_sum_kernel_full_size_batch(sum_full, prec):
+@pytest.mark.parametrize("prec,weighted", [("fp64", False), ("fp64", True), ("fp32c", True)])
+def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted):
     c = sum_full
     D, N, B = c["D"], c["N"], c["B"]
-    tab = oracle.plan_tables(D, N, c["kd"], prec)
+    k = c["kw"] if weighted else c["k"]
+    tab = oracle.plan_tables(D, N, {d: np.array(v["U"] if weighted else v) for d, v in k.items()}, prec)
     say(f"[sum kernel full] D={D} N={N} B={B} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
-    plan = agg.Plan(D, N, c["k"], prec=prec, batch=B)
+    plan = agg.Plan(D, N, k, prec=prec, batch=B)
     n = torch.tensor(c["n0"].reshape(-1), device=DEV)
     f = plan.rhs(n)
     torch.cuda.synchronize()
