@@ -153,3 +153,32 @@ def test_destroy_with_requests_in_flight():
     eng.close()
     assert time.time() - t0 < 30.0
     assert np.array_equal(served_alone(reqs[0], "fp64"), served_alone(reqs[0], "fp64"))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_chunked_and_weighted_requests_in_the_mix(prec):
+    """A request whose row pass runs in chunks (random kernel, u = 76) and one
+    with term weights, served together with small ones: each result equals
+    the same request served alone bit for bit, and agg_solve within tolerance."""
+    N = 65536
+    big = dict(D=4, N=N, kernel=synth.kernel_random(4, N, {2: 4, 3: 8, 4: 11}, 21),
+               n0=synth.n0_uniform_head(N, 5, 16), dt=1e-4, t_end=3e-4)
+    k = synth.kernel_random(3, 2048, 2, 9)
+    rng = np.random.default_rng(10)
+    wk = {d: {"U": U, "weight": rng.uniform(0.5, 1.5, size=2)} for d, U in k.items()}
+    weighted = dict(D=3, N=2048, kernel=wk, n0=synth.n0_uniform_head(2048, 6, 16), dt=1e-3, t_end=5e-3)
+    small = dict(D=2, N=1024, kernel=synth.kernel_ballistic(2, 1024, 0.3), n0=synth.n0_uniform_head(1024, 7, 16),
+                 dt=1e-3, t_end=4e-3)
+    reqs = [big, weighted, small]
+    eng = agg.Engine(0)
+    tickets = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in reqs]
+    res = drain(eng, tickets, [r["N"] for r in reqs])
+    eng.close()
+    for r, t in zip(reqs, tickets):
+        rc, out, _ = res[t]
+        assert rc == agg.AGG_OK
+        assert np.array_equal(out, served_alone(r, prec))
+        ref = alone(r, prec)
+        e = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+        say(f"[mix chunked/weighted] D={r['D']} N={r['N']} {prec}: vs agg_solve {e:.2e}")
+        assert e <= TOL[prec]
