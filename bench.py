@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -53,6 +54,28 @@ def pass_bytes(which: int, N: int, u: int, M: int, cs: int) -> float:
     if which == 2:
         return M * cs + 8.0 * N * (1 + u) + 8.0 * N
     return M * cs + 8.0 * N * (1 + u) + 2 * 8.0 * N + u * M * cs
+
+
+def rhs_flops(N: int, u: int, L: int, tsum: int, T: int) -> float:
+    """Algorithmic flops of one right-hand-side evaluation of one state: u + 1
+    real transforms of length L at 2.5 L log2 L each, the spectral combine over
+    H = L/2 + 1 bins (6 flops per complex product, sum_t (|t| - 1) products,
+    2 flops per term for its coefficient and sum), the weighting and dot
+    products (4 N u) and the loss term with the update (10 N)."""
+    H = L // 2 + 1
+    return (u + 1) * 2.5 * L * math.log2(L) + H * (6 * tsum + 2 * T) + 4.0 * N * u + 10.0 * N
+
+
+def gain_terms(tables, kernel) -> tuple:
+    """(sum over gain terms of (length - 1), number of gain terms) from the flat plan tables."""
+    Tp = int(tables[5])
+    pos = 8 + sum(d * (U.shape[1] if hasattr(U, "shape") else len(U[0])) for d, U in kernel.items())
+    tsum = 0
+    for _ in range(Tp):
+        ln = int(tables[pos])
+        tsum += ln - 1
+        pos += 2 + ln
+    return tsum, Tp
 
 
 def kernel_source_hash() -> str:
@@ -320,6 +343,14 @@ def main():
                 "kernel": PASS_NAMES[dom], "bytes_per_launch": bytes_dom,
                 "us_per_launch": round(prim["passes_us"][dom], 3)}
 
+    tsum, Tp = gain_terms(tables, c["kernel"])
+    F = rhs_flops(N, u, L, tsum, Tp)
+    fpeak = 78.6 if args.prec == "fp64" else 157.3
+    flop_roof = {"flops_per_rhs": round(F), "achieved_tflops": round(F * prim["rhs_per_s"] / 1e12, 3),
+                 "peak_tflops": fpeak, "frac": round(F * prim["rhs_per_s"] / 1e12 / fpeak, 5),
+                 "note": "algorithmic flops; fp32c executes several binary32 operations per flop"
+                         if args.prec == "fp32c" else "algorithmic flops"}
+
     cpu = None
     if args.cpu_seconds > 0:
         log("[bench] cpu baseline (oracle) ...")
@@ -360,6 +391,7 @@ def main():
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,
         "roofline_batched": roof_b,
+        "flop_roofline": flop_roof,
         "cpu_baseline": cpu,
         "serving": serving,
     }
