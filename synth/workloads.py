@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "sizes", "kernel_constant", "kernel_brownian_sum", "kernel_ballistic",
-    "kernel_additive", "kernel_random", "kernel_random_symmetric",
+    "kernel_additive", "kernel_random", "kernel_random_first_mode", "kernel_random_symmetric",
     "kernel_generalized_brownian", "n0_monodisperse", "n0_exponential",
     "n0_uniform_head", "n0_random_dense", "CONFIGS", "config", "build_kernel", "build_n0",
     "serving_requests", "sum_kernel_values", "kernel_expsum",
@@ -101,6 +101,19 @@ def kernel_random(D: int, N: int, ranks, seed: int, low=0.0, high=1.0) -> dict:
     for d in range(2, D + 1):
         R = ranks[d] if isinstance(ranks, dict) else int(ranks)
         out[d] = rng.uniform(low, high, size=(d, R, N))
+    return out
+
+
+def kernel_random_first_mode(D: int, N: int, ranks, seed: int) -> dict:
+    """Random U(0,1) first-mode columns, every other mode 1.0 (one column shared
+    by every rank-one term of every order)."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for d in range(2, D + 1):
+        R = ranks[d] if isinstance(ranks, dict) else int(ranks)
+        U = np.ones((d, R, N), dtype=np.float64)
+        U[0] = rng.uniform(0.0, 1.0, size=(R, N))
+        out[d] = U
     return out
 
 

@@ -272,3 +272,15 @@ def test_term_weights_validation():
     assert e.value.status == agg.AGG_ENONFINITE
     with pytest.raises(ValueError):
         agg.plan_tables(3, 50, {2: {"U": k[2], "weight": np.ones(3)}})
+
+
+def test_chunked_plan_tables_shared_column():
+    """A column shared by every term (the ones column) is listed in every
+    chunk whose terms use it."""
+    D, N = 4, 65536
+    k = synth.kernel_random_first_mode(D, N, 25, 23)
+    ref = oracle_plan(D, N, k, "fp64")
+    assert ref["u"] == 76 and len(ref["chunks"]) >= 2
+    assert np.array_equal(agg.plan_tables(D, N, k, "fp64"), ref["flat"])
+    ones = 25
+    assert sum(ones in cols for cols, _ in ref["chunks"]) >= 2

@@ -91,6 +91,21 @@ def test_chunked_random_kernel(prec):
     assert e <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_chunked_shared_column(prec):
+    """The ones column is used by every term and loaded by every chunk."""
+    D, N = 4, 65536
+    k = synth.kernel_random_first_mode(D, N, 25, 23)
+    tab = oracle.plan_tables(D, N, k, prec)
+    say(f"[chunked shared] D={D} N={N} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
+    n = synth.n0_random_dense(N, 24, decay=1e-4)
+    f = gpu_rhs(D, N, k, n, prec)
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, k, n))
+    e = rel(f, ref)
+    say(f"  rhs err {e:.3e}")
+    assert e <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 def test_term_weights(prec):
     D, N = 4, 40
@@ -130,6 +145,21 @@ def test_chunked_sum_kernel_n65536(sum65536, prec, weighted):
     assert e <= TOL[prec] * c["amp"]
 
 
+def test_chunked_sum_kernel_ragged_n():
+    """A length that is not a power of two (ragged last column group and row)."""
+    D, N = 5, 60001
+    k, alpha, w, fit_err, amp = expsum(D, N)
+    tab = oracle.plan_tables(D, N, dense_kernel(k), "fp64")
+    say(f"[sum kernel ragged] D={D} N={N} u={tab['u']} chunks={len(tab['chunks'])}")
+    assert len(tab["chunks"]) >= 2
+    n = synth.n0_random_dense(N, 51, decay=2e-4)
+    f = gpu_rhs(D, N, k, n, "fp64")
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, dense_kernel(k), n))
+    e = rel(f, ref)
+    say(f"  rhs err {e:.3e}")
+    assert e <= TOL["fp64"] * amp
+
+
 @pytest.fixture(scope="module")
 def sum_full():
     D, N, B = 5, 1 << 20, 4
@@ -139,7 +169,7 @@ def sum_full():
     return dict(D=D, N=N, B=B, k=k, kw=kw, kd=dense_kernel(k), n0=n0, fit_err=fit_err, amp=amp)
 
 
-@pytest.mark.parametrize("prec,weighted", [("fp64", False), ("fp64", True), ("fp32c", True)])
+@pytest.mark.parametrize("prec,weighted", [("fp64", False), ("fp64", True), ("fp32c", True), ("fp32", True)])
 def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted):
     c = sum_full
     D, N, B = c["D"], c["N"], c["B"]
