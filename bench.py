@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--serving", type=int, default=512, help="requests in the serving sample (0 = skip)")
     ap.add_argument("--batch", type=int, default=64, help="states of the batched C3 line (0 = skip)")
     ap.add_argument("--c5", type=int, default=1, help="run the D=5 N=2^20 batch-64 line (0 = skip)")
+    ap.add_argument("--table1", type=int, default=1,
+                    help="run the D=3 pure ternary N=2^19 tensor-train kernel line (0 = skip)")
     ap.add_argument("--c5b", type=int, default=64,
                     help="states of the D=5 N=2^20 compressed (sum i)^(1/2) line (0 = skip)")
     ap.add_argument("--quick", action="store_true",
@@ -332,6 +334,29 @@ def main():
             del n
             torch.cuda.empty_cache()
 
+    table1 = None
+    if args.table1:
+        # the shape of the paper's Table 1: pure ternary aggregation, 3-dimensional
+        # generalized Brownian kernel given by its TT cores, N = 2^19, 100 Heun steps
+        D1, N1, h1, s1 = 3, 1 << 19, 1e-3, 100
+        mus = [1.0 / 3.0, -1.0 / 3.0, 0.0]
+        k1 = {3: agg.tt_expand(N1, synth.brownian_tt_cores(N1, mus))}
+        plan = agg.Plan(D1, N1, k1, "fp64")
+        n = torch.tensor(synth.n0_uniform_head(N1, 3, 16), dtype=torch.float64, device="cuda:0")
+        t1, _ = time_steps(plan, n, h1, s1, 1, torch)
+        tab1 = agg.plan_tables(D1, N1, k1, "fp64")
+        table1 = {"workload": "D=3 pure ternary (d=3 only), generalized Brownian kernel [1/3, -1/3, 0] from "
+                              "its TT cores (ranks 1,3,3,1; 6 paths merged into 1 gain term), N=2^19, "
+                              "n0 uniform on [1,16] seed 3, 100 Heun steps h=1e-3, fp64",
+                  "L": int(tab1[0]), "seconds_100_steps": round(t1, 5), "rhs_per_s": round(2 * s1 / t1, 1),
+                  "paper_seconds_100_steps": {"1 core": 257.80, "128 cores": 12.22},
+                  "paper_context": "Table 1: TT path with MKL ClusterFFT on CPU cores (kernel exponents and "
+                                   "initial data not stated in the paper)"}
+        log(f"[bench] Table-1 shape (D=3 ternary N=2^19 TT Brownian): 100 steps in {t1*1e3:.1f} ms")
+        plan.close()
+        del n
+        torch.cuda.empty_cache()
+
     prim = results[args.prec]
     cs = PREC_BYTES[args.prec]
     # dominant kernel of a time step: the pass with the largest device time
@@ -387,6 +412,7 @@ def main():
         "batched_rhs_per_s": {"batch": args.batch, **batched} if batched else None,
         "d5_n2e20_batch64_rhs_per_s": c5 or None,
         "d5_n2e20_sqrt_sum_kernel_rhs_per_s": c5b,
+        "paper_table1_shape": table1,
         "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,

@@ -188,6 +188,26 @@ agg_status agg_twiddles(int64_t P, double* out);
 agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax, int32_t R, int32_t relative,
                           double* alpha, double* w, double* max_err);
 
+/* Host: a kernel of order d given in tensor-train form (Sec. 2),
+ *   C^(d)_{i_1..i_d} = H^(1)_{i_1} H^(2)_{i_2} ... H^(d)_{i_d},
+ * H^(m)_{i} an r_{m-1} x r_m matrix (r_0 = r_d = 1), written as CP factors: one
+ * rank-one term per rank path (r_1, .., r_{d-1}) whose core columns are all
+ * non-zero, with the column H^(m)_{r_{m-1}, :, r_m} in mode m.  Exact (no
+ * rounding: columns are copied).  Paths are listed in lexicographic order.
+ *   ranks  host, d+1 values r_0..r_d (r_0 = r_d = 1, others in [1, 4096])
+ *   H      host, H[m-1] holds core m as r_{m-1} x r_m columns of N doubles:
+ *          H[m-1][(a*r_m + b)*N + (i-1)] = H^(m)_{a, i, b}
+ *   cap    capacity of U in paths (0: only count)
+ *   U      host out, d*npaths*N doubles, mode-major: mode m's factor array
+ *          (the agg_term U[m-1] of rank npaths) starts at U + (m-1)*npaths*N
+ *   npaths host out, the number of non-zero paths
+ * The planner merges the resulting terms whose column sets agree (for the
+ * generalised Brownian cores of Sec. 2 all d! paths become one term).
+ * Errors: AGG_EINVAL (bad sizes, NULL pointers, cap > 0 but short: npaths is
+ * set), AGG_ENONFINITE (non-finite core entry), AGG_ENOMEM. */
+agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, const double* const* H, int64_t cap,
+                         double* U, int64_t* npaths);
+
 /* ---- serving: continuous batching of whole solves ------------------------- */
 typedef struct {
   int32_t device;          /* HIP device ordinal                                 */

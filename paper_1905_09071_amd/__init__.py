@@ -15,7 +15,7 @@ from ._lib import (AGG_EINVAL, AGG_ENOMEM, AGG_ENONFINITE, AGG_ENOTFOUND, AGG_EU
                    AGG_OK, AGG_PENDING, AGG_MAX_D, PREC, AggError, agg_engine_config,
                    agg_request_stats, agg_solve_stats, agg_term, check, lib)
 
-__all__ = ["Plan", "Engine", "plan_tables", "twiddles", "expsum_fit", "AggError", "PREC", "make_terms"]
+__all__ = ["Plan", "Engine", "plan_tables", "twiddles", "expsum_fit", "tt_expand", "AggError", "PREC", "make_terms"]
 
 
 def make_terms(D: int, N: int, kernel: dict):
@@ -82,6 +82,25 @@ def expsum_fit(f: np.ndarray, smin: int, R: int, relative: bool = False):
     check(lib().agg_expsum_fit(f.ctypes.data_as(dp), int(smin), int(smin) + f.size - 1, int(R), int(bool(relative)),
                                alpha.ctypes.data_as(dp), w.ctypes.data_as(dp), ctypes.byref(err)))
     return alpha[:R], w, err.value
+
+
+def tt_expand(N: int, cores) -> np.ndarray:
+    """CP factors (d, P, N) of a tensor-train kernel given by its d cores, each an
+    array of shape (r_{m-1}, N, r_m) with H[a, i-1, b] = H^(m)_{a, i, b}."""
+    d = len(cores)
+    ranks = [int(np.shape(cores[0])[0])] + [int(np.shape(c)[2]) for c in cores]
+    for m in range(1, d):
+        if np.shape(cores[m])[0] != ranks[m] or np.shape(cores[m])[1] != N:
+            raise ValueError(f"core {m + 1} must have shape (r_{m}, N, r_{m + 1}) = ({ranks[m]}, {N}, r)")
+    r = (ctypes.c_int32 * (d + 1))(*ranks)
+    keep = [np.ascontiguousarray(np.transpose(np.asarray(c, dtype=np.float64), (0, 2, 1))) for c in cores]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * d)(*[k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for k in keep])
+    npaths = ctypes.c_int64(0)
+    check(lib().agg_tt_expand(d, N, r, ptrs, 0, None, ctypes.byref(npaths)))
+    U = np.zeros((d, max(npaths.value, 1), N))
+    check(lib().agg_tt_expand(d, N, r, ptrs, npaths.value, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(npaths)))
+    return U[:, :npaths.value]
 
 
 def twiddles(P: int) -> np.ndarray:

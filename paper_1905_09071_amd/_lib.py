@@ -58,6 +58,8 @@ EXPORTS = [
     ("agg_twiddles", ctypes.c_int32, [ctypes.c_int64, DP]),
     ("agg_expsum_fit", ctypes.c_int32, [DP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                         DP, DP, DP]),
+    ("agg_tt_expand", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(DP), ctypes.c_int64, DP, ctypes.POINTER(ctypes.c_int64)]),
     ("agg_engine_create", ctypes.c_int32, [ctypes.POINTER(agg_engine_config), ctypes.POINTER(ctypes.c_void_p)]),
     ("agg_engine_destroy", ctypes.c_int32, [ctypes.c_void_p]),
     ("agg_submit", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_term),

@@ -183,3 +183,68 @@ extern "C" agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax
   }
   return AGG_OK;
 }
+
+// Tensor-train kernels (Sec. 2: C^(d)_i = H^(1)_{i_1} H^(2)_{i_2} ... H^(d)_{i_d}, the cores
+// H^(m)_{i} being r_{m-1} x r_m matrices, r_0 = r_d = 1).  Summing the matrix product over its
+// rank indices writes the kernel as one rank-one term per rank path (r_1, ..., r_{d-1}), with
+// the column H^(m)_{r_{m-1}, :, r_m} in mode m.  Paths through an all-zero core column add
+// nothing and are skipped, so sparse cores (such as those of the generalised Brownian
+// kernels of Sec. 2) expand to few terms; the planner then merges terms whose columns agree.
+extern "C" agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, const double* const* H,
+                                    int64_t cap, double* U, int64_t* npaths) {
+  if (!ranks || !H || !npaths || d < 1 || d > AGG_MAX_D || N < 1 || cap < 0 || (cap > 0 && !U))
+    return set_error(AGG_EINVAL, "bad argument");
+  if (ranks[0] != 1 || ranks[d] != 1) return set_error(AGG_EINVAL, "ranks[0] and ranks[d] must be 1");
+  for (int m = 1; m < d; ++m)
+    if (ranks[m] < 1 || ranks[m] > 4096) return set_error(AGG_EINVAL, "ranks must lie in [1, 4096]");
+  for (int m = 0; m < d; ++m)
+    if (!H[m]) return set_error(AGG_EINVAL, "NULL core");
+  try {
+    // nonzero[m][a*r_{m+1}+b]: core column (a, b) of core m has a nonzero entry
+    std::vector<std::vector<char>> nz(d);
+    for (int m = 0; m < d; ++m) {
+      const int64_t cols = (int64_t)ranks[m] * ranks[m + 1];
+      nz[m].assign(cols, 0);
+      for (int64_t c = 0; c < cols; ++c) {
+        const double* col = H[m] + c * N;
+        for (int64_t i = 0; i < N; ++i) {
+          if (!std::isfinite(col[i])) return set_error(AGG_ENONFINITE, "non-finite core entry");
+          if (col[i] != 0.0) nz[m][c] = 1;
+        }
+      }
+    }
+    // depth-first enumeration of the paths in lexicographic order of (r_1, ..., r_{d-1})
+    std::vector<int> path(d + 1, 0);
+    int64_t count = 0;
+    std::vector<int64_t> found;   // core column index per mode, d per path
+    auto rec = [&](auto&& self, int m) -> void {
+      if (m == d) {
+        for (int k = 0; k < d; ++k) found.push_back((int64_t)path[k] * ranks[k + 1] + path[k + 1]);
+        ++count;
+        return;
+      }
+      const int nb = ranks[m + 1];
+      for (int b = 0; b < nb; ++b) {
+        if (!nz[m][(int64_t)path[m] * nb + b]) continue;
+        path[m + 1] = b;
+        self(self, m + 1);
+      }
+    };
+    path[0] = 0;
+    rec(rec, 0);
+    *npaths = count;
+    if (U && cap >= count) {
+      for (int64_t p = 0; p < count; ++p)
+        for (int m = 0; m < d; ++m) {
+          const double* src = H[m] + found[(size_t)p * d + m] * N;
+          double* dst = U + ((size_t)m * count + p) * N;
+          for (int64_t i = 0; i < N; ++i) dst[i] = src[i];
+        }
+    } else if (cap > 0) {
+      return set_error(AGG_EINVAL, "output capacity too small (npaths set)");
+    }
+  } catch (const std::bad_alloc&) {
+    return set_error(AGG_ENOMEM, "host allocation failed");
+  }
+  return AGG_OK;
+}

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "sizes", "kernel_constant", "kernel_brownian_sum", "kernel_ballistic",
     "kernel_additive", "kernel_random", "kernel_random_first_mode", "kernel_random_symmetric",
-    "kernel_generalized_brownian", "n0_monodisperse", "n0_exponential",
+    "kernel_generalized_brownian", "brownian_tt_cores", "n0_monodisperse", "n0_exponential",
     "n0_uniform_head", "n0_random_dense", "CONFIGS", "config", "build_kernel", "build_n0",
     "serving_requests", "sum_kernel_values", "kernel_expsum",
 ]
@@ -167,6 +167,31 @@ def kernel_expsum(D: int, N: int, alpha, w, weighted: bool = False) -> dict:
         return {d: {"U": [E] * d, "weight": w} for d in range(2, D + 1)}
     W = E * w[:, None]
     return {d: [W] + [E] * (d - 1) for d in range(2, D + 1)}
+
+
+def brownian_tt_cores(N: int, mus) -> list:
+    """Tensor-train cores of the generalized Brownian kernel C[mu_1..mu_D] (the
+    sum over permutations, Sec. 2) as constructed in the proof of Sec. 2's rank
+    theorem: rank index r_lambda <-> a subset of {1..D} of size lambda (subsets
+    in lexicographic order), ranks C(D, lambda); core lambda+1 maps subset S to
+    S + {xi} with the entry i^mu_xi, and is zero otherwise.  Core m is an array
+    of shape (r_{m-1}, N, r_m)."""
+    from itertools import combinations
+    D = len(mus)
+    s = sizes(N)
+    subsets = [list(combinations(range(D), lam)) for lam in range(D + 1)]
+    index = [{S: k for k, S in enumerate(subs)} for subs in subsets]
+    cores = []
+    for lam in range(D):                       # core lam+1: subsets of size lam -> lam+1
+        H = np.zeros((len(subsets[lam]), N, len(subsets[lam + 1])), dtype=np.float64)
+        for a, S in enumerate(subsets[lam]):
+            for xi in range(D):
+                if xi in S:
+                    continue
+                b = index[lam + 1][tuple(sorted(S + (xi,)))]
+                H[a, :, b] = s ** mus[xi]
+        cores.append(H)
+    return cores
 
 
 def n0_monodisperse(N: int) -> np.ndarray:
