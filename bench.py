@@ -154,6 +154,29 @@ def time_steps(plan, n, dt, steps, warmup, torch):
     return e0.elapsed_time(e1) / 1000.0, wall
 
 
+def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
+    """Device-to-device copy rate (read + write bytes per second, GB/s) of a
+    plain torch copy of `mib` MiB, median of `reps`: the measured ceiling that
+    the roofline is also quoted against."""
+    src = torch.ones(mib * 131072, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    rates = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        rates.append(2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    rates.sort()
+    return rates[len(rates) // 2]
+
+
 def cpu_baseline(c, budget_s: float):
     """The oracle (per-rank numpy FFT evaluation) on the host, bounded sample."""
     import numpy as np
@@ -363,10 +386,13 @@ def main():
     dom = max((1, 3), key=lambda w: prim["passes_us"][w])
     bytes_dom = pass_bytes(dom, N, u, M, cs)
     achieved = bytes_dom / (prim["passes_us"][dom] * 1e-6) / 1e9
+    copy_gbs = copy_bandwidth(torch)
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, args.prec),
                 "kernel": PASS_NAMES[dom], "bytes_per_launch": bytes_dom,
-                "us_per_launch": round(prim["passes_us"][dom], 3)}
+                "us_per_launch": round(prim["passes_us"][dom], 3),
+                "measured_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     tsum, Tp = gain_terms(tables, c["kernel"])
     F = rhs_flops(N, u, L, tsum, Tp)
@@ -416,7 +442,8 @@ def main():
         "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,
-        "roofline_batched": roof_b,
+        "roofline_batched": dict(roof_b, measured_copy_gbs=round(copy_gbs, 1),
+                                 frac_of_copy=round(roof_b["achieved"] / copy_gbs, 4)) if roof_b else None,
         "flop_roofline": flop_roof,
         "cpu_baseline": cpu,
         "serving": serving,
