@@ -204,7 +204,8 @@ agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax, int32_t R
  * The planner merges the resulting terms whose column sets agree (for the
  * generalised Brownian cores of Sec. 2 all d! paths become one term).
  * Errors: AGG_EINVAL (bad sizes, NULL pointers, cap > 0 but short: npaths is
- * set), AGG_ENONFINITE (non-finite core entry), AGG_ENOMEM. */
+ * set), AGG_ENONFINITE (non-finite core entry), AGG_EUNSUPPORTED (more than
+ * 2^20 non-zero paths), AGG_ENOMEM. */
 agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, const double* const* H, int64_t cap,
                          double* U, int64_t* npaths);
 

@@ -190,6 +190,9 @@ extern "C" agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax
 // the column H^(m)_{r_{m-1}, :, r_m} in mode m.  Paths through an all-zero core column add
 // nothing and are skipped, so sparse cores (such as those of the generalised Brownian
 // kernels of Sec. 2) expand to few terms; the planner then merges terms whose columns agree.
+// Paths an expansion may produce (each becomes a rank-one term of d columns).
+constexpr int64_t kMaxPaths = int64_t(1) << 20;
+
 extern "C" agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, const double* const* H,
                                     int64_t cap, double* U, int64_t* npaths) {
   if (!ranks || !H || !npaths || d < 1 || d > AGG_MAX_D || N < 1 || cap < 0 || (cap > 0 && !U))
@@ -217,8 +220,11 @@ extern "C" agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, 
     std::vector<int> path(d + 1, 0);
     int64_t count = 0;
     std::vector<int64_t> found;   // core column index per mode, d per path
+    bool too_many = false;
     auto rec = [&](auto&& self, int m) -> void {
+      if (too_many) return;
       if (m == d) {
+        if (count == kMaxPaths) { too_many = true; return; }
         for (int k = 0; k < d; ++k) found.push_back((int64_t)path[k] * ranks[k + 1] + path[k + 1]);
         ++count;
         return;
@@ -232,6 +238,7 @@ extern "C" agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, 
     };
     path[0] = 0;
     rec(rec, 0);
+    if (too_many) return set_error(AGG_EUNSUPPORTED, "more than 2^20 non-zero rank paths");
     *npaths = count;
     if (U && cap >= count) {
       for (int64_t p = 0; p < count; ++p)

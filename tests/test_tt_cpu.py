@@ -87,3 +87,13 @@ def test_tt_expand_errors():
     with pytest.raises(agg.AggError) as e:
         agg.tt_expand(8, nan)
     assert e.value.status == agg.AGG_ENONFINITE
+
+
+def test_tt_expand_refuses_a_path_explosion():
+    """Dense cores of ranks 128 x 128 x 128 over five modes have 2^21 paths."""
+    N = 2
+    ranks = [1, 128, 128, 128, 1]
+    cores = [np.ones((ranks[m], N, ranks[m + 1])) for m in range(4)]
+    with pytest.raises(agg.AggError) as e:
+        agg.tt_expand(N, cores)
+    assert e.value.status == agg.AGG_EUNSUPPORTED
