@@ -63,6 +63,8 @@ SMALL_CASES = [
     ("N2-d3", 3, 2, lambda D, N: synth.kernel_random(D, N, 2, 13), lambda N: np.array([0.7, 0.4])),
     ("N-less-than-D", 5, 3, lambda D, N: synth.kernel_random(D, N, 1, 14), lambda N: np.array([0.5, 0.3, 0.2])),
     ("N6-d3-wrap", 3, 6, lambda D, N: synth.kernel_random(D, N, 2, 15), lambda N: synth.n0_random_dense(N, 16)),
+    ("random-d6", 6, 9, lambda D, N: synth.kernel_random(D, N, 2, 17), lambda N: synth.n0_random_dense(N, 18)),
+    ("random-d8-max-order", 8, 5, lambda D, N: synth.kernel_random(D, N, 1, 19), lambda N: synth.n0_random_dense(N, 20)),
 ]
 
 
