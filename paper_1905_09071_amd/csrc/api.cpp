@@ -3,8 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -80,6 +85,35 @@ agg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   e = hipStreamSynchronize(s);   // the host vectors are freed on return
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   return AGG_OK;
+}
+
+// Twiddle tables of a launch geometry (w_{M1}, w_{M2} and the two halves of the
+// two-level table of w_L) in a precision's storage format, built once per
+// (L, M1, M2, b, precision) per process: plans and serving requests of equal
+// geometry share them.
+static std::shared_ptr<const std::array<std::vector<unsigned char>, 4>> twiddle_set(const PlanTables& T) {
+  using Key = std::tuple<int64_t, int, int, int, int>;
+  static std::mutex mu;
+  static std::map<Key, std::shared_ptr<const std::array<std::vector<unsigned char>, 4>>> cache;
+  const Key key(T.L, T.M1, T.M2, T.b, T.prec);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const int64_t L = T.L, nlo = int64_t(1) << T.b, nhi = L >> T.b;
+  std::vector<double> w1(2 * T.M1), w2(2 * T.M2), wlo(2 * nlo), whi(2 * nhi);
+  twiddle_table(T.M1, w1.data());
+  twiddle_table(T.M2, w2.data());
+  for (int64_t a = 0; a < nlo; ++a) twiddle_at(L, a, &wlo[2 * a], &wlo[2 * a + 1]);
+  for (int64_t a = 0; a < nhi; ++a) twiddle_at(L, a << T.b, &whi[2 * a], &whi[2 * a + 1]);
+  auto set = std::make_shared<const std::array<std::vector<unsigned char>, 4>>(
+      std::array<std::vector<unsigned char>, 4>{twiddle_bytes(T.prec, w1), twiddle_bytes(T.prec, w2),
+                                                twiddle_bytes(T.prec, wlo), twiddle_bytes(T.prec, whi)});
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache.size() >= 256) cache.clear();   // bounded: geometries are few in practice
+  cache.emplace(key, set);
+  return set;
 }
 
 static double factorial(int d) {
@@ -159,15 +193,8 @@ SharedImage make_shared_image(const PlanTables& T) {
   im.Tp = (int)T.p_ids.size();
   im.Tq = (int)T.q_ids.size();
 
-  // twiddles: w_{M1}, w_{M2}, and the two halves of the two-level table of w_L
-  const int64_t L = T.L, nlo = int64_t(1) << T.b, nhi = L >> T.b;
-  std::vector<double> w1(2 * T.M1), w2(2 * T.M2), wlo(2 * nlo), whi(2 * nhi);
-  twiddle_table(T.M1, w1.data());
-  twiddle_table(T.M2, w2.data());
-  for (int64_t a = 0; a < nlo; ++a) twiddle_at(L, a, &wlo[2 * a], &wlo[2 * a + 1]);
-  for (int64_t a = 0; a < nhi; ++a) twiddle_at(L, a << T.b, &whi[2 * a], &whi[2 * a + 1]);
-  std::vector<unsigned char> tw[4] = {twiddle_bytes(T.prec, w1), twiddle_bytes(T.prec, w2),
-                                      twiddle_bytes(T.prec, wlo), twiddle_bytes(T.prec, whi)};
+  const auto tws = twiddle_set(T);   // held while the image is built
+  const std::array<std::vector<unsigned char>, 4>& tw = *tws;
 
   size_t off = 0;
   const int64_t CL = colorder_len(N, T.M2);
@@ -178,9 +205,17 @@ SharedImage make_shared_image(const PlanTables& T) {
   for (int i = 0; i < 4; ++i) { *two[i] = off; off = align256(off + tw[i].size()); }
   im.bytes.assign(off, 0);
   // factor columns in the column pass's column order (size 0 and sizes past N stay 0)
+  // (size s = 2 j + e, j = j2 + M2 j1, at 2 (j2 J + j1) + e: the loops walk j1, j2)
+  const int64_t J = N / (2 * (int64_t)T.M2) + 1;
   for (int c = 0; c < T.u; ++c) {
     double* dst = (double*)&im.bytes[im.o_cols + (size_t)c * CL * 8];
-    for (int64_t s = 1; s <= N; ++s) dst[colorder_index(s, N, T.M2)] = T.ucols[c][s - 1];
+    const double* src = T.ucols[c].data();
+    for (int64_t j1 = 0; j1 < J; ++j1)
+      for (int64_t j2 = 0; j2 < T.M2; ++j2) {
+        const int64_t s0 = 2 * (j2 + (int64_t)T.M2 * j1), at = 2 * (j2 * J + j1);
+        if (s0 >= 1 && s0 <= N) dst[at] = src[s0 - 1];
+        if (s0 + 1 <= N) dst[at + 1] = src[s0];
+      }
   }
   if (!blob.empty()) std::memcpy(&im.bytes[im.o_tabs], blob.data(), blob.size() * 4);
   if (!coef.empty()) std::memcpy(&im.bytes[im.o_coef], coef.data(), coef.size() * 8);

@@ -25,6 +25,18 @@
 
 namespace agg {
 
+// True when no value is an infinity or a NaN (all exponent bits set), tested
+// on the bit patterns so that the loop vectorises.
+static bool all_finite(const double* x, int64_t n) {
+  uint64_t bad = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t b;
+    std::memcpy(&b, &x[i], 8);
+    bad |= (uint64_t)(((b >> 52) & 0x7ff) == 0x7ff);
+  }
+  return bad == 0;
+}
+
 static int ilog2(int64_t x) {
   int l = 0;
   while ((int64_t(1) << l) < x) ++l;
@@ -59,8 +71,7 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   for (int d = 2; d <= D; ++d) {
     if (!byd[d]) continue;
     for (int m = 0; m < d; ++m)
-      for (int64_t i = 0; i < (int64_t)byd[d]->rank * N; ++i)
-        if (!std::isfinite(byd[d]->U[m][i])) { *err = "non-finite kernel factor"; return AGG_ENONFINITE; }
+      if (!all_finite(byd[d]->U[m], (int64_t)byd[d]->rank * N)) { *err = "non-finite kernel factor"; return AGG_ENONFINITE; }
     if (byd[d]->weight)
       for (int r = 0; r < byd[d]->rank; ++r)
         if (!std::isfinite(byd[d]->weight[r])) { *err = "non-finite kernel weight"; return AGG_ENONFINITE; }
