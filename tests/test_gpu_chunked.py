@@ -162,22 +162,25 @@ def test_chunked_sum_kernel_ragged_n():
 
 @pytest.fixture(scope="module")
 def sum_full():
-    D, N, B = 5, 1 << 20, 4
+    D, N, B = 5, 1 << 20, 64
     k, alpha, w, fit_err, amp = expsum(D, N)
     n0 = np.stack([synth.n0_uniform_head(N, s, 16) for s in range(B)])
     kw = synth.kernel_expsum(D, N, alpha, w, weighted=True)
     return dict(D=D, N=N, B=B, k=k, kw=kw, kd=dense_kernel(k), n0=n0, fit_err=fit_err, amp=amp)
 
 
-@pytest.mark.parametrize("prec,weighted", [("fp64", False), ("fp64", True), ("fp32c", True), ("fp32", True)])
-def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted):
+# batch 64 with term weights is the launch configuration bench.py times; the
+# other cases take 4 states (u = 64 spectra would not fit 64 states in HBM)
+@pytest.mark.parametrize("prec,weighted,B", [("fp64", False, 4), ("fp64", True, 64), ("fp32c", True, 64),
+                                             ("fp32", True, 4)])
+def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted, B):
     c = sum_full
-    D, N, B = c["D"], c["N"], c["B"]
+    D, N = c["D"], c["N"]
     k = c["kw"] if weighted else c["k"]
     tab = oracle.plan_tables(D, N, {d: np.array(v["U"] if weighted else v) for d, v in k.items()}, prec)
     say(f"[sum kernel full] D={D} N={N} B={B} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
     plan = agg.Plan(D, N, k, prec=prec, batch=B)
-    n = torch.tensor(c["n0"].reshape(-1), device=DEV)
+    n = torch.tensor(c["n0"][:B].reshape(-1), device=DEV)
     f = plan.rhs(n)
     torch.cuda.synchronize()
     f = f.cpu().numpy().reshape(B, N)
