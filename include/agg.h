@@ -183,7 +183,7 @@ agg_status agg_twiddles(int64_t P, double* out);
  * alternating sign and magnitudes above max|f| are normal: their cancellation
  * costs accuracy in the lower precisions.
  * Errors: AGG_EINVAL (NULL pointer, smin < 1, smax < smin, R outside [0, 64],
- * a zero f(s) in a relative fit), AGG_ENONFINITE (a non-finite f value),
+ * fewer than R+1 sizes in the range, a zero f(s) in a relative fit), AGG_ENONFINITE (a non-finite f value),
  * AGG_EUNSUPPORTED (no fit found), AGG_ENOMEM. */
 agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax, int32_t R, int32_t relative,
                           double* alpha, double* w, double* max_err);

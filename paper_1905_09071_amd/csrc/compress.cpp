@@ -116,6 +116,7 @@ extern "C" agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax
       if (s >= (double)(smin + 1024) && s <= (double)smax && s > ss.back()) ss.push_back(s);
     }
     const int m = (int)ss.size(), n = R + 1;
+    if (m < n) return set_error(AGG_EINVAL, "fewer sizes in [smin, smax] than terms of the fit");
     std::vector<double> fs(m), base(m, 1.0);   // base: 1/|f| for a relative fit
     for (int i = 0; i < m; ++i) {
       fs[i] = f[(int64_t)ss[i] - smin];

@@ -239,6 +239,9 @@ def test_expsum_fit_special_cases_and_errors():
     with pytest.raises(agg.AggError) as e:
         agg.expsum_fit(f, 1, 65)
     assert e.value.status == agg.AGG_EINVAL
+    with pytest.raises(agg.AggError) as e:      # 5 sizes cannot fix 9 weights
+        agg.expsum_fit(np.ones(5), 1, 8)
+    assert e.value.status == agg.AGG_EINVAL
     g = f.copy()
     g[7] = np.nan
     with pytest.raises(agg.AggError) as e:
