@@ -392,6 +392,7 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   p->stream = (hipStream_t)hip_stream;
   p->trivial = p->tab.u == 0;
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
+  std::vector<std::vector<double>>().swap(p->tab.ucols);   // uploaded: the host copy is not needed
   if ((rc = row_lds_check(p->tab, p->st.ntab, p->st.Tp + p->st.Tq))) goto fail;
   if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
   if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
@@ -424,6 +425,7 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
   if (rc != AGG_OK) return set_error(rc, err);
   agg_plan* p = new agg_plan();
   p->plain = true;
+  std::vector<std::vector<double>>().swap(check.ucols);    // the sub-plans hold their own columns
   p->tab = check;
   p->batch = batch;
   p->stream = (hipStream_t)hip_stream;

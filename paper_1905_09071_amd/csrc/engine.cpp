@@ -524,6 +524,7 @@ agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms
   Engine& g = E->eng;
   // the tables are built on the caller's thread, off the scheduler's path
   r->im = make_shared_image(r->tab);
+  std::vector<std::vector<double>>().swap(r->tab.ucols);   // now in the image
   if ((rc = row_lds_check(r->tab, r->im.ntab, r->im.Tp + r->im.Tq))) return rc;
   r->lay = request_layout(r->tab, r->im.bytes.size());
   if ((int64_t)r->lay.dev_total > g.cfg.mem_budget || r->lay.host_total > g.host.size)
