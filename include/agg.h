@@ -53,6 +53,8 @@ enum {
 
 /* Arithmetic of the spectral path.  AGG_FP32C carries float-float (hi+lo)
  * pairs through every FFT pass, twiddle and product (error-free transforms).
+ * Entry points take the precision as an int32_t holding an agg_precision
+ * value (so that an option bit keeps the argument a valid value).
  * AGG_PLAIN may be OR-ed into the precision of agg_plan_create: the plan then
  * evaluates the right-hand side term by term, one rank-one term (d, r) at a
  * time with its own d transforms (no column shared, not even equal ones),
@@ -93,10 +95,11 @@ typedef struct agg_plan agg_plan;
  * Errors: AGG_EINVAL (D outside [2, AGG_MAX_D], N < 1, bad/duplicate d, rank < 0,
  * NULL factor with rank > 0, batch < 1, unknown precision, out == NULL),
  * AGG_ENONFINITE (a non-finite factor), AGG_EUNSUPPORTED (transform length
- * above 2^23, or too many distinct columns for the two-pass transform),
+ * above 2^23, a gain term with more distinct columns than a row-pass chunk
+ * holds, or row-pass tables beyond a workgroup's LDS),
  * AGG_ENOMEM, AGG_EHIP. */
 agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                           agg_precision prec, int32_t batch, void* hip_stream,
+                           int32_t prec, int32_t batch, void* hip_stream,
                            agg_plan** out);
 agg_status agg_plan_destroy(agg_plan* plan);
 
@@ -154,7 +157,7 @@ agg_status agg_profile_pass(agg_plan* plan, const double* n, int32_t pass, int32
  * (len still set).  agg_twiddles writes exp(-2 pi i e / P) for e = 0..P-1 as
  * interleaved binary64 (re, im) pairs into out[0..2P) (P a power of two). */
 agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                           agg_precision prec, int64_t* out, int64_t cap, int64_t* len);
+                           int32_t prec, int64_t* out, int64_t cap, int64_t* len);
 agg_status agg_twiddles(int64_t P, double* out);
 
 /* ---- host kernel compression (no device is touched) ------------------------
@@ -248,7 +251,7 @@ agg_status agg_engine_destroy(agg_engine* e);
  * AGG_EINVAL when every order has rank 0. */
 agg_status agg_submit(agg_engine* e, int32_t D, int64_t N, const agg_term* terms,
                       int32_t nterms, const double* n0, double dt, double t_end,
-                      agg_precision prec, uint64_t* ticket);
+                      int32_t prec, uint64_t* ticket);
 
 /* Non-blocking.  AGG_PENDING until done; then writes n_out (host, N doubles)
  * and st (nullable), forgets the ticket, and returns the solve's status

@@ -367,7 +367,7 @@ agg_status agg_twiddles(int64_t P, double* out) {
 }
 
 agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                           agg_precision prec, int64_t* out, int64_t cap, int64_t* len) {
+                           int32_t prec, int64_t* out, int64_t cap, int64_t* len) {
   PlanTables T;
   std::string err;
   const int opt = (int)prec;
@@ -408,7 +408,7 @@ fail:
 agg_status agg_plan_destroy(agg_plan* p);
 
 agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                           agg_precision prec_opt, int32_t batch, void* hip_stream, agg_plan** out) {
+                           int32_t prec_opt, int32_t batch, void* hip_stream, agg_plan** out) {
   if (!out) return set_error(AGG_EINVAL, "out is NULL");
   *out = nullptr;
   if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");

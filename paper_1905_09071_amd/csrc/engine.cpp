@@ -508,7 +508,7 @@ agg_status agg_engine_destroy(agg_engine* E) {
 }
 
 agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                      const double* n0, double dt, double t_end, agg_precision prec, uint64_t* ticket) {
+                      const double* n0, double dt, double t_end, int32_t prec, uint64_t* ticket) {
   if (!E || !n0 || !ticket) return set_error(AGG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AGG_EINVAL, "dt must be finite and > 0");
   if (!(t_end >= 0.0) || !std::isfinite(t_end)) return set_error(AGG_EINVAL, "t_end must be finite and >= 0");
