@@ -103,6 +103,26 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
                            agg_plan** out);
 agg_status agg_plan_destroy(agg_plan* plan);
 
+/* Exponential tilting of a binary32 plan's gain transforms (a numerical device,
+ * not in the paper).  The gain term of Sec. 1 is a sum of d-fold convolutions,
+ * and the convolution of inputs scaled by exp(theta s) is the convolution scaled
+ * by exp(theta k): the weighted inputs enter the transforms as
+ * U_c(s) n_s exp(theta s) and the gain leaves them multiplied by exp(-theta k).
+ * For states decaying like exp(-theta k) this flattens the spectra's dynamic
+ * range, so small tail values keep their relative accuracy in binary32 (the
+ * loss term and the state are binary64 either way).  theta = 0 turns it off.
+ * It applies to agg_rhs only: in a time loop the rounding noise that binary32
+ * spectra leave in a state's far tail is lifted by exp(theta s) at every
+ * evaluation and grows (measured: non-finite within 40 Heun steps of the D=3,
+ * N=4096 exp(-k/8) state at theta = 1/12), so agg_rk2_step and agg_solve run
+ * untilted.  The caller keeps the tilted values in range: n_s exp(theta s) for
+ * s <= N and the tilted gain sums up to D N must stay finite in binary32; a
+ * theta below the state's decay rate (e.g. (1 - 1/D) times it) keeps the
+ * tilted D-fold gain bounded.
+ * Errors: AGG_EINVAL (NULL, theta < 0 or non-finite, a plan of another
+ * precision). */
+agg_status agg_plan_set_tilt(agg_plan* plan, double theta);
+
 /* dndt = f(n) for each of the batch states (Sec. 1, the full right-hand side).
  * n, dndt: device, batch*N doubles each, must not overlap.  Asynchronous. */
 agg_status agg_rhs(agg_plan* plan, const double* n, double* dndt);

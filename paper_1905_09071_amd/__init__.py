@@ -163,6 +163,10 @@ class Plan:
         check(lib().agg_rk2_step(self._h, _check_state(n, self.batch * self.N), float(dt)))
         return n
 
+    def set_tilt(self, theta: float):
+        """Exponential tilt of a binary32 plan's gain transforms (see agg.h)."""
+        check(lib().agg_plan_set_tilt(self._h, float(theta)))
+
     def profile_pass(self, n, which: int, reps: int = 50) -> float:
         """Mean device microseconds per launch of one pipeline pass (see agg.h)."""
         us = ctypes.c_double()

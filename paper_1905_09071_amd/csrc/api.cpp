@@ -349,6 +349,7 @@ struct agg_plan {
   hipGraphExec_t gexec = nullptr;
   double* g_state = nullptr;
   double g_dt = 0.0;
+  double tilt = 0.0;          // binary32 plans: exponential tilt of agg_rhs's gain transforms
 };
 
 // Heun steps per captured graph of the time loop.
@@ -457,6 +458,14 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
   return AGG_OK;
 }
 
+agg_status agg_plan_set_tilt(agg_plan* p, double theta) {
+  if (!p) return set_error(AGG_EINVAL, "plan is NULL");
+  if (!(theta >= 0.0) || !std::isfinite(theta)) return set_error(AGG_EINVAL, "theta must be finite and >= 0");
+  if (p->tab.prec != AGG_FP32) return set_error(AGG_EINVAL, "tilting applies to binary32 spectra (AGG_FP32 plans)");
+  p->tilt = theta;   // read by agg_rhs only
+  return AGG_OK;
+}
+
 agg_status agg_plan_destroy(agg_plan* p) {
   if (!p) return AGG_OK;
   (void)hipStreamSynchronize(p->stream);
@@ -469,12 +478,13 @@ agg_status agg_plan_destroy(agg_plan* p) {
 }
 
 static agg_status run_on(agg_plan* p, hipStream_t stream, int mode, double dt, double* state, double* outp,
-                         bool row) {
+                         bool row, double tilt = 0.0) {
   LaunchArgs a = base_args(p->tab, p->st, nullptr, p->batch, true);
   a.base = p->base;
   a.stride = p->stride;
   a.mode = mode;
   a.dt = dt;
+  a.tilt = tilt;
   a.ext_state = state;
   a.ext_out = outp;
   hipError_t e = row ? launch_row(p->tab.prec, a, stream) : launch_col(p->tab.prec, a, stream);
@@ -482,8 +492,9 @@ static agg_status run_on(agg_plan* p, hipStream_t stream, int mode, double dt, d
   return AGG_OK;
 }
 
-static agg_status run(agg_plan* p, int mode, double dt, double* state, double* outp, bool row) {
-  return run_on(p, p->stream, mode, dt, state, outp, row);
+static agg_status run(agg_plan* p, int mode, double dt, double* state, double* outp, bool row,
+                      double tilt = 0.0) {
+  return run_on(p, p->stream, mode, dt, state, outp, row, tilt);
 }
 
 // One full Heun step (stage 1 and stage 2, the latter starting the next step's
@@ -534,14 +545,14 @@ static agg_status step_graph(agg_plan* p, double* n, double h) {
 }
 
 // f(n) accumulated term by term into out (AGG_PLAIN plans)
-static agg_status plain_rhs(agg_plan* p, double* n, double* out) {
+static agg_status plain_rhs(agg_plan* p, double* n, double* out, double tilt = 0.0) {
   hipError_t e = launch_zero(out, p->tab.N * p->batch, p->stream);
   if (e != hipSuccess) return hip_fail(e, "zero launch");
   agg_status rc;
   for (agg_plan* sub : p->subs) {
-    if ((rc = run(sub, CM_FWD, 0.0, n, nullptr, false))) return rc;
+    if ((rc = run(sub, CM_FWD, 0.0, n, nullptr, false, tilt))) return rc;
     if ((rc = run(sub, CM_FWD, 0.0, n, nullptr, true))) return rc;
-    if ((rc = run(sub, CM_RHS_ACC, 0.0, n, out, false))) return rc;
+    if ((rc = run(sub, CM_RHS_ACC, 0.0, n, out, false, tilt))) return rc;
   }
   return AGG_OK;
 }
@@ -549,15 +560,15 @@ static agg_status plain_rhs(agg_plan* p, double* n, double* out) {
 agg_status agg_rhs(agg_plan* p, const double* n, double* dndt) {
   if (!p || !n || !dndt) return set_error(AGG_EINVAL, "NULL argument");
   double* ns = const_cast<double*>(n);
-  if (p->plain) return plain_rhs(p, ns, dndt);
+  if (p->plain) return plain_rhs(p, ns, dndt, p->tilt);
   if (p->trivial) {
     hipError_t e = hipMemsetAsync(dndt, 0, sizeof(double) * p->tab.N * p->batch, p->stream);
     return e == hipSuccess ? AGG_OK : hip_fail(e, "hipMemsetAsync");
   }
   agg_status rc;
-  if ((rc = run(p, CM_FWD, 0.0, ns, nullptr, false))) return rc;
+  if ((rc = run(p, CM_FWD, 0.0, ns, nullptr, false, p->tilt))) return rc;
   if ((rc = run(p, CM_FWD, 0.0, ns, nullptr, true))) return rc;
-  return run(p, CM_RHS, 0.0, ns, dndt, false);
+  return run(p, CM_RHS, 0.0, ns, dndt, false, p->tilt);
 }
 
 static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, double last_dt) {

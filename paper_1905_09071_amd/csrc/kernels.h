@@ -89,6 +89,7 @@ struct LaunchArgs {
   int tab_max;            // largest term-table int blob among the slots
   int coef_max;           // largest coefficient blob (Tp + Tq) among the slots
   int lean;               // column pass variant for launches that fill the GPU
+  double tilt;            // binary32 spectra: inputs weighted by exp(tilt s), gain by exp(-tilt s) (0: off)
 };
 
 constexpr int kColBatch = 4;             // upper bound of LaunchArgs::ub

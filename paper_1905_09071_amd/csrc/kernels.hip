@@ -179,7 +179,12 @@ constexpr bool kColPrune = std::is_same<T, ff>::value ? !LEAN : (std::is_same<T,
 // LEAN (used when a launch already fills the GPU): no factor columns or Heun
 // vectors held in registers, and a register budget that lets two workgroups
 // share a CU, so one workgroup's memory wait overlaps another's arithmetic.
-template <class T, int M1, bool LEAN>
+// TILT (binary32 only): exponential tilting of the transforms' inputs, x[s]
+// exp(tilt s), and of the gain, exp(-tilt s) (a d-fold convolution of tilted
+// inputs is the tilted convolution), so that values decaying like exp(-tilt s)
+// keep their relative accuracy in binary32 spectra; the dot products use the
+// untilted values.
+template <class T, int M1, bool LEAN, bool TILT = false>
 __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchArgs a) {
   constexpr int NT = kColThreads;
   constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
@@ -334,6 +339,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
           double val = 0.0;
           if (s >= 1 && s <= N) {
             double p = s >= 2 ? y[e] * invL : 0.0;
+            if constexpr (TILT) p *= exp(-a.tilt * (double)s);
             double f = p - pe[it][e] * gk[it][e];
             if (mode == CM_RHS) {
               stg(out + (s - 1), f);
@@ -385,6 +391,13 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
       buf[slot * STR + lds_pad(j1)] = v;
     }
   };
+  auto tilted = [&](double x, int it, int e) -> double {
+    if constexpr (TILT) {
+      const int64_t s = pos[it] + e;
+      if (s >= 1 && s <= N) return x * exp(a.tilt * (double)s);
+    }
+    return x;
+  };
   for (int cb = 0; cb < u; cb += a.ub) {
     const int nc = u - cb < a.ub ? u - cb : a.ub;
     // weighted columns x_c = U_c * state for c in [cb, cb+nc)
@@ -399,7 +412,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
             int j1 = idx >> lgg, jl = idx & (g - 1);
             double x0 = uc[q][it][0] * s0[it];
             double x1 = uc[q][it][1] * s1[it];
-            put((q - cb) * g + jl, j1, cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)});
+            put((q - cb) * g + jl, j1, cplx<T>{Real<T>::from_d(tilted(x0, it, 0)), Real<T>::from_d(tilted(x1, it, 1))});
             dsum += x0 + x1;
           }
         }
@@ -418,7 +431,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
           int64_t s = pos[it];
           double x0 = (s >= 1 && s <= N) ? ldg(col + cix[it]) * s0[it] : 0.0;
           double x1 = (s + 1 <= N) ? ldg(col + (cix[it] + 1)) * s1[it] : 0.0;
-          put((c - cb) * g + jl, j1, cplx<T>{Real<T>::from_d(x0), Real<T>::from_d(x1)});
+          put((c - cb) * g + jl, j1, cplx<T>{Real<T>::from_d(tilted(x0, it, 0)), Real<T>::from_d(tilted(x1, it, 1))});
           dsum += x0 + x1;
         }
       }
@@ -1001,16 +1014,16 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(const double* n, int6
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-template <class T, int M1, bool LEAN>
+template <class T, int M1, bool LEAN, bool TILT = false>
 static hipError_t launch_col_v(const LaunchArgs& a, hipStream_t s, size_t smem, dim3 grid) {
   static bool attr_done = false;   // raise the dynamic LDS cap once per instantiation
   if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void*)col_kernel<T, M1, LEAN>,
+    hipError_t e = hipFuncSetAttribute((const void*)col_kernel<T, M1, LEAN, TILT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
     if (e != hipSuccess) return e;
     attr_done = true;
   }
-  hipLaunchKernelGGL((col_kernel<T, M1, LEAN>), grid, dim3(kColThreads), smem, s, a);
+  hipLaunchKernelGGL((col_kernel<T, M1, LEAN, TILT>), grid, dim3(kColThreads), smem, s, a);
   return hipGetLastError();
 }
 
@@ -1022,9 +1035,12 @@ static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
   // from M1 = 1024 the register cap of the lean variant (two workgroups per CU)
   // spills the per-item state to scratch; those launches keep every register
   if constexpr (M1 <= kLeanMaxM1) {
-    if (a.lean) return launch_col_v<T, M1, true>(a, s, ((size_t)M1 + tbuf) * sizeof(cplx<T>), grid);
+    if (a.lean && a.tilt == 0.0) return launch_col_v<T, M1, true>(a, s, ((size_t)M1 + tbuf) * sizeof(cplx<T>), grid);
   }
   constexpr int nbuf = kColPingPong<T, M1, false> ? 2 : 1;
+  if constexpr (std::is_same<T, float>::value) {   // tilted launches take the full variant
+    if (a.tilt != 0.0) return launch_col_v<T, M1, false, true>(a, s, ((size_t)M1 + nbuf * tbuf) * sizeof(cplx<T>), grid);
+  }
   return launch_col_v<T, M1, false>(a, s, ((size_t)M1 + nbuf * tbuf) * sizeof(cplx<T>), grid);
 }
 
