@@ -183,7 +183,7 @@ agg_status agg_twiddles(int64_t P, double* out);
 /* ---- host kernel compression (no device is touched) ------------------------
  * For kernels that depend on the total size only, C^(d)_{i_1..i_d} =
  * f(i_1 + ... + i_d), the paper knows no robust CP construction in general
- * (Sec. 2, remark on the canonical format); this class has one through a 1-D
+ * (Sec. 1, remark on CP decompositions); this class has one through a 1-D
  * exponential sum, because exp(-a (i_1+..+i_d)) = prod_m exp(-a i_m):
  *     f(s) ~ w[0] + sum_{r=1..R} w[r] exp(-alpha[r-1] s),
  * and order d then has CP rank R+1: term r has weight w[r] and the column

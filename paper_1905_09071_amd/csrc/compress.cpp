@@ -1,8 +1,8 @@
 // Host compression of kernels that depend on the total size only,
 // C^(d)(i_1, ..., i_d) = f(i_1 + ... + i_d) (declared in include/agg.h).
 //
-// The paper reports no robust CP method for general kernels (Sec. 2, remark on
-// the canonical format).  For this class a 1-D exponential sum
+// The paper reports no robust CP method for general kernels (Sec. 1, remark on
+// CP decompositions).  For this class a 1-D exponential sum
 //     f(s) ~ w_0 + sum_r w_r exp(-alpha_r s)
 // is already a CP form of every order at once, since exp(-a (i_1 + ... + i_d))
 // is the product of exp(-a i_m) over the modes; the kernel error of every order
