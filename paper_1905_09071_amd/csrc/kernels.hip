@@ -538,8 +538,10 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
   const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
   const int64_t lmask = (int64_t(1) << a.b) - 1;
   // combine mapping: with few distinct columns (non-lean variant) two adjacent
-  // lanes share a bin pair, one per bin; otherwise one thread per bin pair
-  const bool split = !LEAN && u <= kRowRegCols;
+  // lanes share a bin pair, one per bin; otherwise one thread per bin pair.
+  // The longest rows keep the LDS mapping: the register mapping spilled there
+  // and measured 7% slower.
+  const bool split = !LEAN && M2 < 2048 && u <= kRowRegCols;
   cplx<T> wkh[CPT], wkl[CPT];   // w_L^k of this thread's combine units (two table halves)
 #pragma unroll
   for (int i = 0; i < CPT; ++i) {
