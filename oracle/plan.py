@@ -21,8 +21,9 @@ P6  Two-pass split: lg = log2 M; M1 = 2^ceil(lg/2), M2 = M/M1.  With cs = 16
     bytes per stored complex (fp64, fp32c) or 8 (fp32): while u*2*M2*cs > 64 KiB
     and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048.
 P7  Column tile: g = min(M2, max(1, 1024 / M1)) adjacent columns per workgroup.
-P8  Row-pass chunks, only when u*2*M2*cs > 144 KiB after P6 (the combine cannot
-    hold every column's two rows at once): cmax = floor(148 KiB / (2*(M2 +
+P8  Row-pass chunks, only when u*2*(M2 + M2/16)*cs + (M2 <= 512 ? M2*cs : 0)
+    > 144 KiB after P6 (the combine cannot hold every column's two padded rows
+    and the row twiddles at once): cmax = floor(148 KiB / (2*(M2 +
     M2/16)*cs)) columns per chunk (rows padded by one slot in 16 in LDS).  Gain terms are visited in the order of their ascending
     tuple of distinct ids, ties kept in P4 order; a chunk takes the next term
     while the union of its distinct ids and the term's stays within cmax, else
@@ -104,7 +105,7 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = 
     g = min(M2, max(1, 1024 // M1))
 
     chunks = []
-    if u * 2 * M2 * cs > 147456:
+    if u * 2 * (M2 + M2 // 16) * cs + (M2 * cs if M2 <= 512 else 0) > 147456:
         cmax = 151552 // (2 * (M2 + M2 // 16) * cs)
         order = sorted(range(len(pterms)), key=lambda t: (tuple(sorted(set(pterms[t][0]))), t))
         cols, terms = set(), []

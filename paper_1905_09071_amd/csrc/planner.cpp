@@ -10,7 +10,8 @@
 //  - two-pass split M = M1*M2 of the half-length complex transform with the
 //    row working set u*2*M2 complex values capped at 64 KiB while M1 <= 2048;
 //  - column tile g = min(M2, max(1, 1024/M1));
-//  - when the row working set still exceeds 144 KiB, the row pass combines the
+//  - when the row working set (rows at their padded LDS length, plus the row
+//    twiddles for M2 <= 512) still exceeds 144 KiB, the row pass combines the
 //    gain terms chunk by chunk: terms visited by their ascending distinct ids
 //    (ties in gain-term order), a chunk growing while the union of its ids
 //    stays within 148 KiB / (2*(M2 + M2/16)*cs) columns.
@@ -152,7 +153,10 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1));
   P.b = (ilog2(L) + 1) / 2;
 
-  if ((int64_t)P.u * 2 * M2 * cs > 147456) {
+  // chunks when the unchunked row pass's rows (at their padded LDS length) and
+  // its twiddle table would not leave room for the term tables
+  const int64_t row_need = (int64_t)P.u * 2 * (M2 + M2 / 16) * cs + (M2 <= 512 ? M2 * cs : 0);
+  if (row_need > 147456) {
     // chunk capacity: 148 KiB of rows at the row pass's padded LDS length
     P.cmax = (int)(151552 / (2 * (M2 + M2 / 16) * cs));
     std::vector<std::pair<std::vector<int>, int>> order;   // (distinct ids, term)

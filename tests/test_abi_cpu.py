@@ -179,7 +179,7 @@ def test_chunked_plan_tables_bit_exact(D, N, prec, weighted):
     got = agg.plan_tables(D, N, k, prec)
     assert np.array_equal(got, ref["flat"])
     M2, cs = ref["M2"], 8 if prec == "fp32" else 16
-    if ref["u"] * 2 * M2 * cs > 147456:
+    if ref["u"] * 2 * (M2 + M2 // 16) * cs + (M2 * cs if M2 <= 512 else 0) > 147456:
         assert len(ref["chunks"]) >= 2
         for cols, terms in ref["chunks"]:
             assert len(cols) <= 151552 // (2 * (M2 + M2 // 16) * cs)
@@ -287,3 +287,14 @@ def test_chunked_plan_tables_shared_column():
     assert np.array_equal(agg.plan_tables(D, N, k, "fp64"), ref["flat"])
     ones = 25
     assert sum(ones in cols for cols, _ in ref["chunks"]) >= 2
+
+
+def test_chunk_rule_counts_padded_rows_and_twiddles():
+    """u = 9 columns at M2 = 512 fill exactly 144 KiB unpadded; with the LDS
+    padding and the row twiddles they do not, so the plan takes two chunks
+    (the unchunked row pass would not fit a workgroup's LDS)."""
+    D, N = 3, 1 << 19
+    k = synth.kernel_random(D, N, {2: 3, 3: 1}, 31)
+    ref = oracle_plan(D, N, k, "fp64")
+    assert ref["u"] == 9 and ref["M2"] == 512 and len(ref["chunks"]) == 2
+    assert np.array_equal(agg.plan_tables(D, N, k, "fp64"), ref["flat"])

@@ -106,6 +106,19 @@ def test_chunked_shared_column(prec):
     assert e <= TOL[prec]
 
 
+def test_chunked_at_the_padded_lds_limit():
+    """u = 9 columns at M2 = 512 (D = 3, N = 2^19): chunked because the padded
+    rows and the row twiddles would not fit the unchunked row pass."""
+    D, N = 3, 1 << 19
+    k = synth.kernel_random(D, N, {2: 3, 3: 1}, 31)
+    n = synth.n0_random_dense(N, 32, decay=1e-4)
+    f = gpu_rhs(D, N, k, n, "fp64")
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, k, n))
+    e = rel(f, ref)
+    say(f"[chunk limit] D={D} N={N} u=9: rhs err {e:.3e}")
+    assert e <= TOL["fp64"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 def test_term_weights(prec):
     D, N = 4, 40
