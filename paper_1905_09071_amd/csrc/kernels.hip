@@ -841,9 +841,11 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
     const int t1 = chunked ? cht[h + 1] : uniform_int(sd.Tp);
     lds_barrier();   // the previous chunk's combine is done with X
     const int nload = nc * nrows * M2;
+    // unrolled so that several loads are in flight before their LDS stores wait
+#pragma unroll 8
     for (int idx = tid; idx < nload; idx += NT) {
       const int cr = idx / M2, k2 = idx - cr * M2;
-      const int c = cr / nrows, rr = cr - c * nrows;
+      const int c = nrows == 2 ? cr >> 1 : cr, rr = cr - c * nrows;
       const int gc = chunked ? chcols[c0 + c] : c;
       X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)gc * M + (int64_t)row_of(rr) * M2 + k2));
     }
