@@ -100,7 +100,7 @@ def measured_traffic(which: int, prec: str):
     return t.get("bytes_per_launch", {}).get(f"{prec}:{which}")
 
 
-def write_traffic(fetch_csv: str, write_csv: str, copy_mib: int, prec: str) -> dict:
+def write_traffic(fetch_csv: str, write_csv: str, copy_mib: int, prec: str, out_path: str = None) -> dict:
     """Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch) of `bench.py --quick --copy-probe MIB` into bytes per launch of the
     column and row passes, calibrated by the counters of the plain device copy
@@ -133,7 +133,7 @@ def write_traffic(fetch_csv: str, write_csv: str, copy_mib: int, prec: str) -> d
          "copy_fetch_KiB": copy_f, "copy_write_KiB": copy_w,
          "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
          "bytes_per_launch": per_launch, "median_KiB_per_dispatch": med}
-    with open(os.path.join(ROOT, "profiles", "traffic_c3.json"), "w") as f:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic_c3.json"), "w") as f:
         json.dump(t, f, indent=1)
     return t
 
