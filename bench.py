@@ -10,7 +10,13 @@ t = 0.5 solve.  The state is resident in HBM before the timed region starts.
 Prints ONE JSON line.  `value` is right-hand-side evaluations per second in
 the primary precision (float-float compensated by default); the binary64 and
 binary32 rates of the same workload are reported beside it, with the serving
-sample's latency percentiles and the oracle's CPU rate.
+sample's latency percentiles, the oracle's CPU rate and the factored CPU
+version's rate on every host thread.
+
+Every GPU line also states its error against the binary64 oracle.  The GPU legs
+keep the outputs they check (computed outside the timed regions); the one leg
+that runs the oracle (`cpu_legs`, after all GPU work) times it, times the
+factored CPU version, and computes the reference values of those outputs.
 """
 from __future__ import annotations
 
@@ -179,7 +185,6 @@ def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
 
 def cpu_baseline(c, budget_s: float):
     """The oracle (per-rank numpy FFT evaluation) on the host, bounded sample."""
-    import numpy as np
     import oracle
     import synth
     n = synth.n0_random_dense(c["N"], 5, decay=1e-4)
@@ -191,8 +196,95 @@ def cpu_baseline(c, budget_s: float):
         el = time.perf_counter() - t0
         if el >= budget_s or evals >= 400:
             break
-    _ = np
     return evals / el, evals, el
+
+
+def cpu_factored(c, budget_s: float):
+    """The factored CPU version (oracle/factored.c: distinct columns, own binary64
+    FFT, OpenMP over every host thread) on the same workload, bounded sample."""
+    import oracle
+    import synth
+    n = synth.n0_random_dense(c["N"], 5, decay=1e-4)
+    oracle.rhs_factored(c["D"], c["N"], c["kernel"], n)      # first call: threads, pages
+    evals, threads = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        _, threads = oracle.rhs_factored(c["D"], c["N"], c["kernel"], n)
+        evals += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or evals >= 5000:
+            break
+    return evals / el, evals, el, threads
+
+
+def rel_err(got, ref) -> float:
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(got) - ref)) / max(float(np.max(np.abs(ref))), 1e-300))
+
+
+def dense_factors(kernel) -> dict:
+    """A kernel dict as the oracle takes it: (d, R, N) factor arrays without
+    weights (a rank's weight multiplies its mode-1 column)."""
+    import numpy as np
+    out = {}
+    for d, v in kernel.items():
+        w = None
+        if isinstance(v, dict):
+            w, v = v.get("weight"), v["U"]
+        U = np.array([np.asarray(x, dtype=np.float64) for x in v])
+        if w is not None:
+            U[0] = U[0] * np.asarray(w, dtype=np.float64)[:, None]
+        out[d] = U
+    return out
+
+
+def oracle_reference(chk: dict):
+    """Reference value of one recorded GPU output.  kind "rhs": the oracle's
+    right-hand side of chk["n"] (per-rank FFT evaluation; with "kmax", per-rank
+    direct convolutions up to kmax, exact for a state whose support lies in
+    [1, kmax/D]); kind "solve": the oracle's Heun trajectory from chk["n"] to
+    chk["t_end"] with step chk["dt"]."""
+    import numpy as np
+    import oracle
+    D, N, k = chk["D"], chk["N"], dense_factors(chk["kernel"])
+
+    def rhs(v):
+        if chk.get("kmax"):
+            p, q = oracle.rhs_conv(D, N, k, v, kmax=chk["kmax"])
+            p[:, chk["kmax"]:] = 0.0
+            return oracle.total_rhs(p, q)
+        return oracle.total_rhs(*oracle.rhs_fft(D, N, k, v))
+
+    if chk["kind"] == "rhs":
+        return rhs(chk["n"])
+    _ = np
+    return oracle.heun_solve(rhs, chk["n"], chk["dt"], chk["t_end"])
+
+
+def cpu_legs(c, budget_s: float, checks: dict, log=print):
+    """Everything that runs the oracle, after all GPU work: the oracle's CPU rate,
+    the factored CPU version's rate, and the error of every recorded GPU output
+    (``checks``: name -> (GPU output, reference spec)) against the oracle."""
+    import os as _os
+    out = {"cpu_baseline": None, "cpu_factored": None, "errors": {}}
+    if budget_s > 0:
+        rate, evals, el = cpu_baseline(c, budget_s)
+        out["cpu_baseline"] = {"value": round(rate, 4), "unit": "RHS evals/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{evals} oracle RHS evaluations (per-rank numpy FFT, D=4 N=65536, "
+                                         f"dense state) in {el:.1f} s on one host thread"}
+        log(f"[bench] cpu oracle: {rate:.2f} RHS/s")
+        rate, evals, el, th = cpu_factored(c, budget_s)
+        out["cpu_factored"] = {"value": round(rate, 3), "unit": "RHS evals/s", "cores": th, "kind": "factored",
+                               "host_cpus": _os.cpu_count(),
+                               "sample": f"{evals} RHS evaluations of the factored CPU version (oracle/factored.c: "
+                                         f"3 distinct columns, own radix-2 binary64 FFT of length 2^18, "
+                                         f"OpenMP) in {el:.1f} s on {th} threads, D=4 N=65536 dense state"}
+        log(f"[bench] cpu factored: {rate:.2f} RHS/s on {th} threads")
+    for name, (got, chk) in checks.items():
+        t0 = time.perf_counter()
+        out["errors"][name] = float(f"{rel_err(got, oracle_reference(chk)):.3e}")
+        log(f"[bench] accuracy {name}: {out['errors'][name]:.3e} ({time.perf_counter() - t0:.1f} s)")
+    return out
 
 
 def main():
@@ -248,6 +340,8 @@ def main():
         del src, dst
 
     results = {}
+    checks = {}    # name -> (GPU output, oracle reference spec); checked in cpu_legs
+    nd = synth.n0_random_dense(N, 5, decay=1e-4)   # dense state of the accuracy checks
     order = [args.prec] + [p for p in ("fp64", "fp32", "fp32c") if p != args.prec]
     if args.quick:
         order = [args.prec]
@@ -266,6 +360,8 @@ def main():
             continue
         passes = {w: plan.profile_pass(n, w, reps=200) for w in (0, 1, 2, 3)}
         results[prec] = dict(seconds=t_gpu, wall=t_wall, rhs_per_s=rate, passes_us=passes)
+        f = plan.rhs(torch.tensor(nd, dtype=torch.float64, device="cuda:0"))
+        checks[f"c3_rhs_{prec}"] = (f.cpu().numpy(), dict(kind="rhs", D=D, N=N, kernel=c["kernel"], n=nd))
         log(f"[bench] {prec}: {args.steps} steps in {t_gpu*1e3:.2f} ms (wall {t_wall*1e3:.2f}) -> "
             f"{rate:.1f} RHS/s; pass us: " + ", ".join(f"{w}:{v:.2f}" for w, v in passes.items()))
         plan.close()
@@ -297,6 +393,9 @@ def main():
             bsteps = 20
             t_b, _ = time_steps(plan, n, dt, bsteps, 2, torch)
             batched[prec] = round(2 * bsteps * args.batch / t_b, 1)
+            f = plan.rhs(torch.tensor(np.tile(nd, args.batch), dtype=torch.float64, device="cuda:0"))
+            checks[f"c3_batch_rhs_{prec}_last_member"] = (
+                f.cpu().numpy()[(args.batch - 1) * N:], dict(kind="rhs", D=D, N=N, kernel=c["kernel"], n=nd))
             log(f"[bench] C3 batch {args.batch} {prec}: {2 * bsteps * args.batch / t_b:.1f} RHS/s")
             if prec == args.prec:
                 # the same byte model at saturation: B states per launch
@@ -320,6 +419,11 @@ def main():
             s5 = 10
             t5, _ = time_steps(plan, n, cc["dt"], s5, 1, torch)
             c5[prec] = round(2 * s5 * B5 / t5, 2)
+            f = plan.rhs(torch.tensor(cc["n0"].reshape(-1), dtype=torch.float64, device="cuda:0"))
+            f = f.cpu().numpy().reshape(B5, cc["N"])
+            for b in (0, B5 - 1):
+                checks[f"d5_n2e20_rhs_{prec}_member{b}"] = (
+                    f[b], dict(kind="rhs", D=cc["D"], N=cc["N"], kernel=cc["kernel"], n=cc["n0"][b], kmax=80))
             log(f"[bench] D=5 N=2^20 batch {B5} {prec}: {s5} steps in {t5*1e3:.1f} ms -> {c5[prec]} RHS/s")
             plan.close()
             del n
@@ -351,6 +455,9 @@ def main():
             torch.cuda.synchronize()
             t5 = e0.elapsed_time(e1) / 1000.0
             c5b[prec] = round(2 * s5 * B / t5, 2)
+            f = plan.rhs(torch.tensor(n0.reshape(-1), dtype=torch.float64, device="cuda:0"))
+            checks[f"d5_n2e20_sqrt_sum_rhs_{prec}_member0"] = (
+                f.cpu().numpy()[:N5], dict(kind="rhs", D=D5, N=N5, kernel=k5, n=n0[0], kmax=80))
             log(f"[bench] D=5 N=2^20 sqrt-sum kernel (rank 32, u=32) batch {B} {prec}: {s5} steps in "
                 f"{t5*1e3:.1f} ms -> {c5b[prec]} RHS/s")
             plan.close()
@@ -368,6 +475,9 @@ def main():
         n = torch.tensor(synth.n0_uniform_head(N1, 3, 16), dtype=torch.float64, device="cuda:0")
         t1, _ = time_steps(plan, n, h1, s1, 1, torch)
         tab1 = agg.plan_tables(D1, N1, k1, "fp64")
+        nt1 = synth.n0_uniform_head(N1, 3, 16)
+        f = plan.rhs(torch.tensor(nt1, dtype=torch.float64, device="cuda:0"))
+        checks["table1_shape_rhs_fp64"] = (f.cpu().numpy(), dict(kind="rhs", D=D1, N=N1, kernel=k1, n=nt1, kmax=48))
         table1 = {"workload": "D=3 pure ternary (d=3 only), generalized Brownian kernel [1/3, -1/3, 0] from "
                               "its TT cores (ranks 1,3,3,1; 6 paths merged into 1 gain term), N=2^19, "
                               "n0 uniform on [1,16] seed 3, 100 Heun steps h=1e-3, fp64",
@@ -402,18 +512,23 @@ def main():
                  "note": "algorithmic flops; fp32c executes several binary32 operations per flop"
                          if args.prec == "fp32c" else "algorithmic flops"}
 
-    cpu = None
-    if args.cpu_seconds > 0:
-        log("[bench] cpu baseline (oracle) ...")
-        rate, evals, el = cpu_baseline(c, args.cpu_seconds)
-        cpu = {"value": round(rate, 4), "unit": "RHS evals/s", "cores": 1, "kind": "oracle",
-               "sample": f"{evals} oracle RHS evaluations (per-rank numpy FFT, D=4 N=65536, dense state) "
-                         f"in {el:.1f} s on one host thread"}
-
     serving = None
     if args.serving > 0:
         from serving_bench import run_serving
-        serving = run_serving(args.serving, log=log)
+        serving, served = run_serving(args.serving, log=log)
+        for i, (out, r) in enumerate(served):
+            checks[f"serving_sample_{i}"] = (out, dict(kind="solve", D=r["D"], N=r["N"], kernel=r["kernel"],
+                                                      n=r["n0"], dt=r["dt"], t_end=r["t_end"]))
+
+    # the one leg that runs the oracle: CPU rates and the reference values
+    legs = cpu_legs(c, args.cpu_seconds, checks, log=log)
+    cpu = legs["cpu_baseline"]
+    errors = legs["errors"]
+    if serving is not None:
+        se = [v for k, v in errors.items() if k.startswith("serving_sample_")]
+        serving["max_err_vs_oracle_sampled"] = max(se) if se else None
+        serving["accuracy_sample"] = (f"{len(se)} served results (fp32c) against the oracle's Heun trajectory, "
+                                      "max_k |n - n_ref| / max_k n_ref")
 
     ms_per_step = prim["seconds"] / args.steps * 1e3
     line = {
@@ -446,6 +561,11 @@ def main():
                                  frac_of_copy=round(roof_b["achieved"] / copy_gbs, 4)) if roof_b else None,
         "flop_roofline": flop_roof,
         "cpu_baseline": cpu,
+        "cpu_factored": legs["cpu_factored"],
+        "gpu_vs_cpu_factored": (round(prim["rhs_per_s"] / legs["cpu_factored"]["value"], 1)
+                                if legs["cpu_factored"] else None),
+        "rhs_err_vs_oracle": errors,
+        "err_norm": "max_k |f - f_ref| / max_k |f_ref| per RHS (the oracle's binary64 evaluation)",
         "serving": serving,
     }
     _ = np

@@ -11,6 +11,8 @@ modelling multi-particle interactions"):
                    library step, one product of spectra per (d, r)
 * ``rhs_sum_kernel`` the definitions specialised to kernels that depend on the
                    total size only (no factorisation involved)
+* ``rhs_factored`` the same method in C with its own FFT and OpenMP threads:
+                   the factored CPU version GPU throughput is compared with
 * ``heun_solve``   explicit second-order Runge-Kutta (Heun) time stepping (Sec. 3)
 * closed forms     constant-kernel zeroth moment, binary constant kernel
 * ``plan_tables``  the written integer plan rules, implemented independently
@@ -20,7 +22,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline leg
 may import anything from here.  The oracle imports nothing from the product
 package and the product package imports nothing from here.
 """
-from .native import rhs_direct, rhs_conv, build_native  # noqa: F401
+from .native import rhs_direct, rhs_conv, rhs_factored, build_native  # noqa: F401
 from .spectral import rhs_fft, total_rhs  # noqa: F401
 from .heun import heun_solve, time_grid  # noqa: F401
 from .closed_forms import (m0_constant_kernel_d3, m0_rhs_constant_kernel,  # noqa: F401

@@ -14,18 +14,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "core.c")
 _LIB = os.path.join(_HERE, "_oracle_core.so")
+_FSRC = os.path.join(_HERE, "factored.c")
+_FLIB = os.path.join(_HERE, "_oracle_factored.so")
 _lib = None
+_flib = None
+
+
+def _gcc(src, lib, force, opt):
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp%d" % os.getpid()
+        cmd = ["gcc", opt, "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", src, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib)
+    return lib
 
 
 def build_native(force: bool = False) -> str:
-    """Compile core.c into oracle/_oracle_core.so (gcc, no GPU involved)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile core.c into oracle/_oracle_core.so and factored.c into
+    oracle/_oracle_factored.so (gcc, no GPU involved)."""
+    _gcc(_FSRC, _FLIB, force, "-O3")
+    return _gcc(_SRC, _LIB, force, "-O2")
 
 
 def _get():
@@ -89,3 +98,31 @@ def rhs_conv(D: int, N: int, kernel: dict, n: np.ndarray, kmax: int = 0):
         raise ValueError("oracle_rhs_conv rejected its arguments")
     del keep
     return p, q
+
+
+def _get_factored():
+    global _flib
+    if _flib is None:
+        build_native()
+        lib = ctypes.CDLL(_FLIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.factored_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(dp), dp, dp, ctypes.POINTER(ctypes.c_int)]
+        _flib = lib
+    return _flib
+
+
+def rhs_factored(D: int, N: int, kernel: dict, n: np.ndarray):
+    """The factored CPU evaluation (factored.c, OpenMP): returns (f, threads)
+    with f[k-1] = sum_d (p_k^(d) + q_k^(d))."""
+    lib = _get_factored()
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    R, F, keep = _marshal(D, N, kernel)
+    f = np.zeros(N)
+    th = ctypes.c_int(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.factored_rhs(D, N, R, F, n.ctypes.data_as(dp), f.ctypes.data_as(dp), ctypes.byref(th))
+    if rc != 0:
+        raise ValueError(f"factored_rhs failed ({rc})")
+    del keep
+    return f, th.value

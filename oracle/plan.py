@@ -19,7 +19,8 @@ P5  Loss terms: for each (d, r) the key is (d, id of mode d, ascending-sorted id
     Coefficient = multiplicity / (d-1)!.
 P6  Two-pass split: lg = log2 M; M1 = 2^ceil(lg/2), M2 = M/M1.  With cs = 16
     bytes per stored complex (fp64, fp32c) or 8 (fp32): while u*2*M2*cs > 64 KiB
-    and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048.
+    and M1 < 2048, double M1 and halve M2.  Unsupported if then M1 > 2048 or
+    M2 < 2 (more than 1024 distinct columns at the shortest lengths).
 P7  Column tile: g = min(M2, max(1, 1024 / M1)) adjacent columns per workgroup.
 P8  Row-pass chunks, only when u*2*(M2 + M2/16)*cs + (M2 <= 512 ? M2*cs : 0)
     > 144 KiB after P6 (the combine cannot hold every column's two padded rows
@@ -102,6 +103,8 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = 
         M2 //= 2
     if M1 > 2048:
         raise Unsupported(f"no two-pass split for L={L}")
+    if M2 < 2:
+        raise Unsupported(f"u={u} distinct columns leave rows of one value at L={L}")
     g = min(M2, max(1, 1024 // M1))
 
     chunks = []

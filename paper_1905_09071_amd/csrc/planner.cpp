@@ -149,6 +149,7 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   int64_t M2 = P.M / M1;
   while ((int64_t)P.u * 2 * M2 * cs > 65536 && M1 < 2048) { M1 *= 2; M2 /= 2; }
   if (M1 > 2048) { *err = "no two-pass split at this length"; return AGG_EUNSUPPORTED; }
+  if (M2 < 2) { *err = "too many distinct factor columns for the row pass at this length"; return AGG_EUNSUPPORTED; }
   P.M1 = (int)M1; P.M2 = (int)M2;
   P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1));
   P.b = (ilog2(L) + 1) / 2;

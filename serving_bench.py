@@ -31,7 +31,10 @@ def _drain(eng, tickets, Ns, deadline_s=600.0):
     return done
 
 
-def run_serving(count: int, steps_range=(20, 200), log=print, seed: int = 4):
+def run_serving(count: int, steps_range=(20, 200), log=print, seed: int = 4, nsample: int = 6):
+    """Returns (summary, sample): the sample is ``nsample`` served results with
+    their requests (the cheapest ones to re-solve on the host: smallest N times
+    steps), which bench.py checks against the oracle after all GPU work."""
     import paper_1905_09071_amd as agg
     import synth
 
@@ -60,6 +63,9 @@ def run_serving(count: int, steps_range=(20, 200), log=print, seed: int = 4):
         done = _drain(eng, tickets, [r["N"] for r in reqs])
         span = time.perf_counter() - t0
         lat = np.array([(v[2].t_finish - v[2].t_submit) for v in done.values()])
+        cost = [r["N"] * round(r["t_end"] / r["dt"]) * (1 << (2 * r["D"])) for r in reqs]
+        pick = sorted(range(count), key=lambda i: cost[i])[:nsample]
+        sample = [(done[tickets[i]][1], reqs[i]) for i in pick if done[tickets[i]][0] == 0]
         queue = np.array([(v[2].t_admit - v[2].t_submit) for v in done.values()])
         steps = int(sum(v[2].steps for v in done.values()))
         bad = sum(1 for v in done.values() if v[0] != 0)
@@ -78,6 +84,6 @@ def run_serving(count: int, steps_range=(20, 200), log=print, seed: int = 4):
             "failed": bad,
         }
         log(f"[serving] poisson at {lam:.1f}/s: p50 {res['p50_latency_ms']} ms, p99 {res['p99_latency_ms']} ms")
-        return res
+        return res, sample
     finally:
         eng.close()

@@ -1,8 +1,8 @@
 """Writes c3_trajectory_t0.5.txt: the oracle's n(t = 0.5) for the D=4, N=65536
 ballistic workload (1000 Heun steps of h = 5e-4 from the seeded initial state),
 sampled.  Calls only the oracle (per-rank numpy FFT evaluation of the Sec. 1
-sums, Heun stepping of Sec. 3) and the seeded input generators.  About five
-minutes on one host thread.
+sums, Heun stepping of Sec. 3) and the seeded input generators.  About 25
+minutes on one host thread (the written file's header records the time taken).
 
     python tests/golden/make_c3_trajectory.py
 """

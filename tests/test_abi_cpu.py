@@ -298,3 +298,14 @@ def test_chunk_rule_counts_padded_rows_and_twiddles():
     ref = oracle_plan(D, N, k, "fp64")
     assert ref["u"] == 9 and ref["M2"] == 512 and len(ref["chunks"]) == 2
     assert np.array_equal(agg.plan_tables(D, N, k, "fp64"), ref["flat"])
+
+
+def test_planner_refuses_rows_of_one_value():
+    """More than 1024 distinct columns at L = 16: refused at planning (the row
+    pass has no launch for rows of one value), as the oracle's twin refuses it."""
+    k = synth.kernel_random(2, 2, 600, 3)
+    with pytest.raises(agg.AggError) as e:
+        agg.plan_tables(2, 2, k, "fp64")
+    assert e.value.status == agg.AGG_EUNSUPPORTED
+    k = synth.kernel_random(2, 2, 500, 3)
+    assert np.array_equal(agg.plan_tables(2, 2, k, "fp64"), np.array(oracle_plan(2, 2, k, "fp64")["flat"]))

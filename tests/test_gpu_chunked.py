@@ -16,11 +16,14 @@ Cases:
     Heun step too.
 
 Tolerances.  The exponential-sum weights alternate in sign and exceed the
-kernel's values, so the spectral path rounds terms larger than their sum: the
-rounding bound of each precision is scaled by the amplification
-A = max_s sum_r |w_r exp(-alpha_r s)| / max_s |f(s)| (at least 1).  The error
-of the compressed kernel itself (the fit) is reported against the exact
-function through the function-of-sum identity, not asserted."""
+kernel's values, so the spectral path rounds terms larger than their sum, by
+the amplification A = max_s sum_r |w_r exp(-alpha_r s)| / max_s |f(s)| (about
+91 for the rank-32 fit).  Binary64 and float-float spectra still meet their
+bars unscaled (1e-12 and 1e-10 relative to the largest output); binary32
+spectra are held to 1e-5 times A (they miss 1e-5 itself on this kernel at
+N = 2^20).  The error of the compressed kernel itself (the fit) is reported
+against the exact function through the function-of-sum identity, not
+asserted."""
 import sys
 
 import numpy as np
@@ -41,6 +44,11 @@ TOL = {"fp64": 1e-12, "fp32c": 1e-10, "fp32": 1e-5}
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def bound(prec, amp):
+    """Per-RHS bar of a precision on the compressed kernel (see the module notes)."""
+    return TOL[prec] * (amp if prec == "fp32" else 1.0)
 
 
 def rel(a, b):
@@ -155,7 +163,7 @@ def test_chunked_sum_kernel_n65536(sum65536, prec, weighted):
     f = gpu_rhs(c["D"], c["N"], k, c["n"], prec)
     e = rel(f, c["ref"])
     say(f"  rhs err vs CP oracle {e:.3e}; vs the exact kernel {rel(f, c['exact']):.3e}")
-    assert e <= TOL[prec] * c["amp"]
+    assert e <= bound(prec, c["amp"])
 
 
 def test_chunked_sum_kernel_ragged_n():
@@ -170,7 +178,7 @@ def test_chunked_sum_kernel_ragged_n():
     ref = oracle.total_rhs(*oracle.rhs_fft(D, N, dense_kernel(k), n))
     e = rel(f, ref)
     say(f"  rhs err {e:.3e}")
-    assert e <= TOL["fp64"] * amp
+    assert e <= bound("fp64", amp)
 
 
 @pytest.fixture(scope="module")
@@ -204,7 +212,7 @@ def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted, B):
         pe, qe = oracle.rhs_sum_kernel(D, 16 * D, fv, c["n0"][b][:16 * D])
         ex = oracle.total_rhs(pe, qe)
         say(f"  member {b}: rhs err {e:.3e}; vs the exact kernel {rel(f[b, :16 * D], ex):.3e}")
-        assert e <= TOL[prec] * c["amp"]
+        assert e <= bound(prec, c["amp"])
     h = 1e-4
     plan.rk2_step(n, h)
     torch.cuda.synchronize()
@@ -213,5 +221,5 @@ def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted, B):
     ref = oracle.heun_solve(lambda v: rhs_short(D, N, c["kd"], v, 400), c["n0"][0], h, h)
     e = rel(nb[0], ref)
     say(f"  heun member 0: err {e:.3e}")
-    assert e <= TOL[prec] * c["amp"]
+    assert e <= bound(prec, c["amp"])
     plan.close()

@@ -75,6 +75,48 @@ def test_c5_batch_rhs_and_step(c5, prec):
     plan.close()
 
 
+def _c5a_members():
+    from conftest import golden_path
+    kv, rows = {}, []
+    with open(golden_path("c5a_members_t5e-6.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("# MEMBER "):
+                t = line[2:].split()
+                kv[int(t[1])] = {t[i]: float(t[i + 1]) for i in range(2, len(t), 2)}
+            elif line and not line.startswith("#"):
+                a, b, c = line.split()
+                rows.append((int(a), float(b), float(c)))
+    return kv, rows
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_c5a_configured_solve_vs_oracle_members(c5, prec):
+    """The configured C5a solve (the whole batch of 64, 10 Heun steps of
+    h = 5e-7, graph-replayed) against the oracle's trajectories of members 0 and
+    37 (tests/golden/c5a_members_t5e-6.txt, written by the committed script
+    beside it): sampled n_k and the first two moments."""
+    kv, rows = _c5a_members()
+    D, N, B = c5["D"], c5["N"], c5["n0"].shape[0]
+    say(f"[C5a solve] D={D} N={N} B={B} prec={prec}: 10 steps")
+    plan = agg.Plan(D, N, c5["kernel"], prec, batch=B)
+    n = torch.tensor(c5["n0"].reshape(-1), device="cuda:0")
+    st = plan.solve(n, c5["dt"], c5["t_end"])
+    assert st.steps == 10
+    torch.cuda.synchronize()
+    got = n.cpu().numpy().reshape(B, N)
+    plan.close()
+    idx = np.array([r[0] for r in rows])
+    sizes = np.arange(1, N + 1, dtype=np.float64)
+    for col, b in ((1, 0), (2, 37)):
+        ref = np.array([r[col] for r in rows])
+        e = float(np.max(np.abs(got[b][idx - 1] - ref)) / kv[b]["MAX"])
+        m0 = abs(got[b].sum() - kv[b]["M0"]) / kv[b]["M0"]
+        m1 = abs((sizes * got[b]).sum() - kv[b]["M1"]) / kv[b]["M1"]
+        say(f"  member {b}: n(t_end) err {e:.3e}, M0 {m0:.2e}, M1 {m1:.2e}")
+        assert e <= 1e-10 and m0 <= 1e-10 and m1 <= 1e-10
+
+
 def test_c5_dense_state_identities(c5):
     D, N = c5["D"], c5["N"]
     k = c5["kernel"]

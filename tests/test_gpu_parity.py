@@ -445,3 +445,46 @@ def test_c3_whole_solve_vs_oracle_trajectory(prec):
     say(f"  n(t_end) err {e:.3e}, M0 {m0:.2e}, M1 {m1:.2e}")
     tol = {"fp64": 1e-10, "fp32c": 1e-10, "fp32": 1e-4}[prec]
     assert e <= tol and m0 <= tol and m1 <= tol
+
+
+def _c2_reference():
+    kv, rows = {}, []
+    from conftest import golden_path
+    with open(golden_path("c2_trajectory_t10.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("# M0 ") or line.startswith("# M1 ") or line.startswith("# MAX "):
+                key, val = line[2:].split()
+                kv[key] = float(val)
+            elif line and not line.startswith("#"):
+                a, b = line.split()
+                rows.append((int(a), float(b)))
+    return kv, rows
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_c2_whole_solve_vs_oracle_trajectory(prec):
+    """The full C2 solve as configured (10000 Heun steps of h = 1e-3 to t = 10,
+    graph-replayed) against the oracle's trajectory
+    (tests/golden/c2_trajectory_t10.txt, written by the committed script beside
+    it): sampled n_k and the first two moments.  Past t = 4 mass leaves through
+    the truncation at N, so M1 is compared with the oracle's, not with M1(0)."""
+    kv, rows = _c2_reference()
+    c = synth.config("C2")
+    D, N = c["D"], c["N"]
+    say(f"[c2 solve] D={D} N={N} prec={prec}: 10000 steps")
+    plan = agg.Plan(D, N, c["kernel"], prec)
+    n = torch.tensor(c["n0"], device=DEV)
+    plan.solve(n, c["dt"], c["t_end"])
+    torch.cuda.synchronize()
+    got = n.cpu().numpy()
+    plan.close()
+    idx = np.array([k for k, _ in rows])
+    ref = np.array([v for _, v in rows])
+    e = float(np.max(np.abs(got[idx - 1] - ref)) / kv["MAX"])
+    sizes = np.arange(1, N + 1, dtype=np.float64)
+    m0 = abs(got.sum() - kv["M0"]) / kv["M0"]
+    m1 = abs((sizes * got).sum() - kv["M1"]) / kv["M1"]
+    say(f"  n(t_end) err {e:.3e}, M0 {m0:.2e}, M1 {m1:.2e}")
+    tol = {"fp64": 1e-10, "fp32c": 1e-10, "fp32": 1e-4}[prec]
+    assert e <= tol and m0 <= tol and m1 <= tol

@@ -1,16 +1,19 @@
 """Serving engine on the GPU: requests of uneven N, D, kernel and length run
 concurrently (continuous batching); each result equals, bit for bit, the same
-request served alone by the engine, and agrees with agg_solve of the request
-within the parity tolerance (agg_solve may narrow the column group of a small
-launch, which regroups the binary64 partial dot products); admission,
-rejection and ticket handling."""
+request served alone by the engine, agrees with the oracle's Heun trajectory of
+the request (per-rank FFT evaluation of the Sec. 1 sums, Heun stepping of
+Sec. 3) and with agg_solve of the request within the parity tolerance
+(agg_solve may narrow the column group of a small launch, which regroups the
+binary64 partial dot products); admission, rejection and ticket handling."""
 import sys
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
+from conftest import dense_kernel
 
 torch = pytest.importorskip("torch")
 agg = pytest.importorskip("paper_1905_09071_amd")
@@ -33,6 +36,23 @@ def alone(r, prec):
 
 
 TOL = {"fp64": 1e-12, "fp32c": 1e-10}
+_ORACLE = {}
+
+
+def oracle_solve(r):
+    """The oracle's n(t_end) of a request (cached per request: both precisions
+    are checked against the same binary64 trajectory)."""
+    key = (r["D"], r["N"], r.get("a"), r["dt"], r["t_end"], hash(np.asarray(r["n0"]).tobytes()))
+    if key not in _ORACLE:
+        k = dense_kernel(r["kernel"])
+        rhs = lambda v: oracle.total_rhs(*oracle.rhs_fft(r["D"], r["N"], k, v))
+        _ORACLE[key] = oracle.heun_solve(rhs, r["n0"], r["dt"], r["t_end"])
+    return _ORACLE[key]
+
+
+def vs_oracle(out, r):
+    ref = oracle_solve(r)
+    return float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
 
 
 def served_alone(r, prec):
@@ -75,8 +95,10 @@ def test_mixed_requests_equal_alone(prec):
         assert rc == agg.AGG_OK
         ref = alone(r, prec)
         solo = served_alone(r, prec)
+        eo = vs_oracle(out, r)
         say(f"[serve] D={r['D']} N={r['N']} a={r['a']:.2f} steps={st.steps} "
-            f"maxdiff vs agg_solve={np.max(np.abs(out - ref)):.3e}")
+            f"maxdiff vs agg_solve={np.max(np.abs(out - ref)):.3e}, rel err vs oracle {eo:.3e}")
+        assert eo <= TOL[prec]
         assert st.steps == len(__import__("oracle").time_grid(r["dt"], r["t_end"]))
         assert np.array_equal(out, solo)       # slot arithmetic is independent of neighbours
         assert np.max(np.abs(out - ref)) <= TOL[prec] * np.max(np.abs(ref))
@@ -180,5 +202,6 @@ def test_chunked_and_weighted_requests_in_the_mix(prec):
         assert np.array_equal(out, served_alone(r, prec))
         ref = alone(r, prec)
         e = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
-        say(f"[mix chunked/weighted] D={r['D']} N={r['N']} {prec}: vs agg_solve {e:.2e}")
-        assert e <= TOL[prec]
+        eo = vs_oracle(out, r)
+        say(f"[mix chunked/weighted] D={r['D']} N={r['N']} {prec}: vs agg_solve {e:.2e}, vs oracle {eo:.2e}")
+        assert e <= TOL[prec] and eo <= TOL[prec]

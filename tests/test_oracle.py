@@ -295,3 +295,31 @@ def test_sum_kernel_fft_branch_matches_direct_branch():
         power = np.convolve(power, x)
         expect = -np.dot(fv[:power.size], power) / math.factorial(d - 1)
         assert abs(q[d].sum() - expect) <= 1e-12 * abs(expect)
+
+
+@pytest.mark.parametrize("D,N,kf,seed", [
+    (2, 50, lambda D, N: synth.kernel_random(D, N, 3, 61), 62),
+    (3, 37, lambda D, N: synth.kernel_random(D, N, 2, 63), 64),
+    (4, 21, lambda D, N: synth.kernel_ballistic(D, N, 0.4), 65),
+    (5, 13, lambda D, N: synth.kernel_additive(D, N), 66),
+    (3, 1, lambda D, N: synth.kernel_random(D, N, 2, 67), 68),
+])
+def test_factored_cpu_version_equals_literal_sums(D, N, kf, seed):
+    """The factored CPU evaluation (own FFT, OpenMP) against the literal sums."""
+    k = kf(D, N)
+    n = synth.n0_random_dense(N, seed)
+    ref = oracle.total_rhs(*oracle.rhs_direct(D, N, k, n))
+    f, threads = oracle.rhs_factored(D, N, k, n)
+    assert threads >= 1
+    assert np.max(np.abs(f - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_factored_cpu_version_equals_direct_convolutions():
+    """At a size where the literal sums are out of reach: against the per-rank
+    direct convolutions, on a dense state (ballistic D=4 kernel, N=3000)."""
+    D, N = 4, 3000
+    k = synth.kernel_ballistic(D, N, 0.4)
+    n = synth.n0_random_dense(N, 69, decay=1e-3)
+    ref = oracle.total_rhs(*oracle.rhs_conv(D, N, k, n))
+    f, _ = oracle.rhs_factored(D, N, k, n)
+    assert np.max(np.abs(f - ref)) <= 1e-12 * np.max(np.abs(ref))

@@ -57,3 +57,27 @@ def test_split_rule_and_unsupported():
     assert (t["L"], t["M1"], t["M2"], t["u"]) == (1 << 23, 2048, 2048, 2)
     with pytest.raises(Unsupported):
         plan_tables(5, 1 << 20, synth.kernel_random(5, 1 << 20, 1, 0), "fp64")
+
+
+def test_chunked_tables_by_hand():
+    """D = 3, N = 2^19, random ranks R_2 = 3, R_3 = 1 (nine distinct columns).
+    P2: L = 2^21 (3N - 1 = 1572863).  P6: 9*2*1024*16 B > 64 KiB at M1 = 1024,
+    so M1 = 2048, M2 = 512 (the loop stops at M1 = 2048).  P7: g = 1.
+    P8: rows 9*2*544*16 + 512*16 = 164864 B > 144 KiB, so chunks of
+    cmax = floor(151552 / (2*544*16)) = 8 columns.  Gain terms {0,3}, {1,4},
+    {2,5}, {6,7,8} in visiting order: the first three share a chunk of six
+    columns; adding {6,7,8} would need nine, so it opens the second chunk."""
+    N = 1 << 19
+    t = plan_tables(3, N, synth.kernel_random(3, N, {2: 3, 3: 1}, 31), "fp64")
+    assert (t["L"], t["M1"], t["M2"], t["g"], t["u"], t["De"]) == (1 << 21, 2048, 512, 1, 9, 3)
+    assert t["colmap"] == list(range(9))
+    assert t["pterms"] == [((0, 3), 1), ((1, 4), 1), ((2, 5), 1), ((6, 7, 8), 1)]
+    assert t["qterms"] == [((2, 3, (0,)), 1), ((2, 4, (1,)), 1), ((2, 5, (2,)), 1), ((3, 8, (6, 7)), 1)]
+    assert t["chunks"] == [([0, 1, 2, 3, 4, 5], [0, 1, 2]), ([6, 7, 8], [3])]
+
+
+def test_too_many_columns_for_the_shortest_rows():
+    """P6: 1200 distinct columns at L = 16 would leave rows of one value."""
+    with pytest.raises(Unsupported):
+        plan_tables(2, 2, synth.kernel_random(2, 2, 600, 3), "fp64")
+    assert plan_tables(2, 2, synth.kernel_random(2, 2, 500, 3), "fp64")["M2"] == 2
