@@ -127,6 +127,28 @@ agg_status agg_plan_set_tilt(agg_plan* plan, double theta);
  * n, dndt: device, batch*N doubles each, must not overlap.  Asynchronous. */
 agg_status agg_rhs(agg_plan* plan, const double* n, double* dndt);
 
+/* agg_rhs without plan-owned workspace, for callers that cannot allocate
+ * device memory when they evaluate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same launches and results as
+ * agg_rhs (bit for bit when batch equals the plan's batch), with the per-state
+ * workspace taken from a static device array of the library of
+ * AGG_NOALLOC_SCRATCH_BYTES bytes on each device the library runs on, held
+ * until the process ends.  Nothing is allocated or freed by the call.
+ *   plan   a shared-column plan (not AGG_PLAIN) created beforehand; its factor
+ *          copies, tables and twiddles are read, its own workspace is not used
+ *   n      device, batch*N doubles (first `batch` states of the plan's layout)
+ *   dndt   device, batch*N doubles, must not overlap n
+ *   batch  1 <= batch <= the plan's batch
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (no part of it needs to start at zero): calls that overlap on one
+ * GPU (different streams, threads or plans) race and must be ordered by the
+ * caller.  Stream-ordered and asynchronous on the plan's stream.
+ * Errors: AGG_EINVAL (NULL argument, AGG_PLAIN plan, batch out of range),
+ * AGG_EUNSUPPORTED (batch times the per-state workspace, u*M + M stored complex
+ * values plus u*(M2+1) doubles, exceeds the array), AGG_EHIP. */
+#define AGG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+agg_status agg_rhs_noalloc(agg_plan* plan, const double* n, double* dndt, int32_t batch);
+
 /* One Heun step in place (Sec. 3: explicit second-order Runge-Kutta, two
  * right-hand-side evaluations): k1 = f(n), n~ = n + dt k1, k2 = f(n~),
  * n <- n + dt/2 (k1 + k2).  n: device, batch*N.  dt > 0 and finite.  Async. */

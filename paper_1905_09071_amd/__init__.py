@@ -159,6 +159,13 @@ class Plan:
         check(lib().agg_rhs(self._h, _check_state(n, self.batch * self.N), _check_state(out, self.batch * self.N)))
         return out
 
+    def rhs_noalloc(self, n, out, batch: int = None):
+        """agg_rhs_noalloc: f(n) for the first ``batch`` states with the library's
+        static workspace (no device allocation by the call)."""
+        b = self.batch if batch is None else int(batch)
+        check(lib().agg_rhs_noalloc(self._h, _check_state(n, b * self.N), _check_state(out, b * self.N), b))
+        return out
+
     def rk2_step(self, n, dt: float):
         check(lib().agg_rk2_step(self._h, _check_state(n, self.batch * self.N), float(dt)))
         return n

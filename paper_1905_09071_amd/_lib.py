@@ -48,6 +48,7 @@ EXPORTS = [
     ("agg_plan_destroy", ctypes.c_int32, [ctypes.c_void_p]),
     ("agg_plan_set_tilt", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double]),
     ("agg_rhs", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("agg_rhs_noalloc", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     ("agg_rk2_step", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
     ("agg_solve", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(agg_solve_stats)]),

@@ -26,6 +26,7 @@ DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "
           "-packed-fp32-ops", "-fno-fast-math", "-ffp-contract=fast-honor-pragmas"]
 SOURCES = [
     ("kernels.hip", True),
+    ("noalloc.hip", True),
     ("api.cpp", False),
     ("planner.cpp", False),
     ("engine.cpp", False),

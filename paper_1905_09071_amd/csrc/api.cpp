@@ -333,6 +333,7 @@ struct agg_plan {
   SharedTables st;
   DeviceArena arena;
   int batch = 1;
+  int device = 0;             // HIP device current at creation (owns every buffer)
   hipStream_t stream = nullptr;
   SlotDesc base;              // slot 0; slot b is base moved by b*stride
   SlotStride stride;
@@ -392,6 +393,7 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   p->batch = batch;
   p->stream = (hipStream_t)hip_stream;
   p->trivial = p->tab.u == 0;
+  if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
   if ((rc = build_shared(p->tab, p->stream, p->arena, &p->st))) goto fail;
   std::vector<std::vector<double>>().swap(p->tab.ucols);   // uploaded: the host copy is not needed
   if ((rc = row_lds_check(p->tab, p->st.ntab, p->st.Tp + p->st.Tq))) goto fail;
@@ -556,6 +558,70 @@ static agg_status plain_rhs(agg_plan* p, double* n, double* out, double tilt = 0
   }
   return AGG_OK;
 }
+
+}  // extern "C"
+
+namespace agg {
+
+// Per-state workspace of one evaluation (forward spectra Z1, combined spectrum V,
+// partial dot products, loss weights) carved from one caller-provided block:
+// the bytes one state needs, each part 256-byte aligned.
+size_t rhs_workspace_bytes(const agg_plan* p) {
+  const size_t cs = complex_bytes(p->tab.prec);
+  return align256((size_t)p->tab.u * p->tab.M * cs) + align256((size_t)p->tab.M * cs) +
+         align256((size_t)p->tab.u * p->tab.M2 * 8) + align256((size_t)std::max(p->tab.u, 1) * 8);
+}
+
+int plan_device(const agg_plan* p) { return p->device; }
+
+// f(n) for `batch` states of the plan's kernel set with the per-state buffers taken
+// from `ws` (batch * rhs_workspace_bytes bytes, device memory of the plan's device)
+// instead of the plan's own: the same launches as agg_rhs.  Nothing is allocated;
+// no buffer needs to start at zero (every workspace value is written before it is
+// read within the evaluation).
+agg_status rhs_in_workspace(agg_plan* p, const double* n, double* dndt, int batch, void* ws) {
+  if (p->trivial) {
+    hipError_t e = launch_zero(dndt, p->tab.N * batch, p->stream);
+    return e == hipSuccess ? AGG_OK : hip_fail(e, "zero launch");
+  }
+  const size_t cs = complex_bytes(p->tab.prec);
+  SlotDesc sd = p->base;
+  SlotStride st;
+  std::memset(&st, 0, sizeof(st));
+  char* b = (char*)ws;
+  const size_t per = rhs_workspace_bytes(p);
+  sd.Z1 = b;
+  b += align256((size_t)p->tab.u * p->tab.M * cs);
+  sd.V = b;
+  b += align256((size_t)p->tab.M * cs);
+  sd.dots = (double*)b;
+  b += align256((size_t)p->tab.u * p->tab.M2 * 8);
+  sd.G = (double*)b;
+  sd.k1 = nullptr;     // Heun vectors: not touched by a plain evaluation
+  sd.ntil = nullptr;
+  st.Z1 = st.V = st.dots = st.G = (int64_t)per;
+  double* ns = const_cast<double*>(n);
+  static const int modes[3] = {CM_FWD, CM_FWD, CM_RHS};
+  for (int k = 0; k < 3; ++k) {
+    LaunchArgs a = base_args(p->tab, p->st, nullptr, batch, true);
+    a.base = sd;
+    a.stride = st;
+    a.mode = modes[k];
+    a.tilt = k == 1 ? 0.0 : p->tilt;
+    a.ext_state = ns;
+    a.ext_out = dndt;
+    hipError_t e = k == 1 ? launch_row(p->tab.prec, a, p->stream) : launch_col(p->tab.prec, a, p->stream);
+    if (e != hipSuccess) return hip_fail(e, k == 1 ? "row pass launch" : "column pass launch");
+  }
+  return AGG_OK;
+}
+
+bool plan_is_plain(const agg_plan* p) { return p->plain; }
+int plan_batch(const agg_plan* p) { return p->batch; }
+
+}  // namespace agg
+
+extern "C" {
 
 agg_status agg_rhs(agg_plan* p, const double* n, double* dndt) {
   if (!p || !n || !dndt) return set_error(AGG_EINVAL, "NULL argument");

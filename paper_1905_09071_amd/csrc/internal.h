@@ -60,6 +60,13 @@ agg_status row_lds_check(const PlanTables& T, int ntab, int ncoef);
 LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots,
                      bool spread = false);
 
+// api.cpp: the plain evaluation with caller-provided per-state workspace
+size_t rhs_workspace_bytes(const agg_plan* p);
+agg_status rhs_in_workspace(agg_plan* p, const double* n, double* dndt, int batch, void* ws);
+int plan_device(const agg_plan* p);
+int plan_batch(const agg_plan* p);
+bool plan_is_plain(const agg_plan* p);
+
 // kernels.hip
 hipError_t launch_col(int prec, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_row(int prec, const LaunchArgs& a, hipStream_t s);
