@@ -398,7 +398,7 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   std::vector<std::vector<double>>().swap(p->tab.ucols);   // uploaded: the host copy is not needed
   if ((rc = row_lds_check(p->tab, p->st.ntab, p->st.Tp + p->st.Tq))) goto fail;
   if ((rc = build_slots(p->tab, p->st, p->arena, batch, &p->base, &p->stride))) goto fail;
-  if ((rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part))) goto fail;
+  if ((rc = p->arena.alloc(sizeof(double) * 5 * p->moment_blocks, (void**)&p->d_part))) goto fail;
   if ((rc = p->arena.alloc(sizeof(double) * p->tab.N * batch, (void**)&p->d_scratch))) goto fail;
   *out = p;
   return AGG_OK;
@@ -449,7 +449,7 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
   if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * N * batch, (void**)&p->k1p);
   if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * N * batch, (void**)&p->k2p);
   if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * N * batch, (void**)&p->ntp);
-  if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * 3 * p->moment_blocks, (void**)&p->d_part);
+  if (rc == AGG_OK) rc = p->arena.alloc(sizeof(double) * 5 * p->moment_blocks, (void**)&p->d_part);
   if (rc != AGG_OK) {
     std::string keep = g_err;
     agg_plan_destroy(p);
@@ -688,14 +688,26 @@ static agg_status moments(agg_plan* p, const double* n, double* m0, double* m1, 
   int64_t total = p->tab.N * p->batch;
   hipError_t e = launch_moments(n, total, p->tab.N, p->d_part, p->moment_blocks, p->stream);
   if (e != hipSuccess) return hip_fail(e, "moments launch");
-  std::vector<double> h(3 * p->moment_blocks);
+  std::vector<double> h(5 * p->moment_blocks);
   e = hipMemcpyAsync(h.data(), p->d_part, h.size() * 8, hipMemcpyDeviceToHost, p->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  double a0 = 0, a1 = 0, a2 = 0;
-  for (int b = 0; b < p->moment_blocks; ++b) { a0 += h[3 * b]; a1 += h[3 * b + 1]; a2 += h[3 * b + 2]; }
-  *m0 = a0; *m1 = a1; *nonfinite = (int64_t)a2;
+  // the block partials are combined with the same compensated summation
+  double s0 = 0, c0 = 0, s1 = 0, c1 = 0, bad = 0;
+  auto add = [](double& s, double& c, double x) {
+    const double t = s + x, bb = t - s;
+    c += (s - (t - bb)) + (x - bb);
+    s = t;
+  };
+  for (int b = 0; b < p->moment_blocks; ++b) {
+    add(s0, c0, h[5 * b]);
+    c0 += h[5 * b + 1];
+    add(s1, c1, h[5 * b + 2]);
+    c1 += h[5 * b + 3];
+    bad += h[5 * b + 4];
+  }
+  *m0 = s0 + c0; *m1 = s1 + c1; *nonfinite = (int64_t)bad;
   return AGG_OK;
 }
 

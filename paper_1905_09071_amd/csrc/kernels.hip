@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "fft_lds.h"
+#include "fft_wave.h"
 #include "kernels.h"
 
 namespace agg {
@@ -495,7 +496,12 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
   constexpr int UPT = (M2 + NT - 1) / NT;       // combine units per thread
   constexpr int HPT = (2 * M2 + NT - 1) / NT;   // combine half-units per thread (two lanes per unit)
   constexpr int CPT = UPT > HPT ? UPT : HPT;
-  constexpr int VPT = (2 * M2 + NT - 1) / NT;   // output values per thread
+  // rows of 256 and 512 values: each transform is held by one wavefront in
+  // registers (fft_wave.h), loaded from and stored to device memory directly;
+  // other lengths run the workgroup-wide LDS stages
+  constexpr bool WAVE = M2 == 256 || (M2 == 512 && !(LEAN && std::is_same<T, ff>::value));   // (that one spilled)
+  constexpr int E = WAVE ? M2 / 64 : 1;         // values per lane of a wavefront transform
+  constexpr int VPT = WAVE ? E : (2 * M2 + NT - 1) / NT;   // output values per thread
   extern __shared__ __align__(16) unsigned char smem[];
 
   const int M1 = a.M1;
@@ -508,7 +514,9 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
   const int u = sd.u;
   const int64_t M = (int64_t)M1 * M2;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // the wavefront index is uniform over the wavefront: held in a scalar
+  // register, loops over a wavefront's jobs are uniform branches
+  const int lane = tid & 63, wave = uniform_int(tid >> 6);
 
   // LDS layout
   cplx<T>* twl = (cplx<T>*)smem;                         // M2 when TW_LDS
@@ -527,12 +535,28 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
   // everything this work item reads from HBM is requested up front, in the
   // order it is needed (completions are counted in issue order)
   const cplx<T>* Z1 = (const cplx<T>*)sd.Z1;
-  const int nload = u * nrows * M2;
+  // wavefront transforms: job j = (column j / nrows, row j mod nrows); wavefront
+  // w takes jobs w, w + NWAVE, ..., holding the next job's row in registers
+  // while it transforms the current one
+  const int njobs = u * nrows;
+  cplx<T> vcur[E], vnext[E];
+  auto load_job = [&](int j, cplx<T>(&v)[E]) {
+    const int c = j / nrows, rr = j - c * nrows;
+    const cplx<T>* src = Z1 + ((size_t)c * M + (int64_t)row_of(rr) * M2 + lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ldg(src + 64 * e);
+  };
+  if constexpr (WAVE) {
+    if (wave < njobs) load_job(wave, vcur);
+    if (wave + NWAVE < njobs) load_job(wave + NWAVE, vnext);
+  } else {
+    const int nload = u * nrows * M2;
 #pragma unroll 8
-  for (int idx = tid; idx < nload; idx += NT) {
-    int cr = idx / M2, k2 = idx - cr * M2;
-    int c = cr / nrows, rr = cr - c * nrows;
-    X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)c * M + (int64_t)row_of(rr) * M2 + k2));
+    for (int idx = tid; idx < nload; idx += NT) {
+      int cr = idx / M2, k2 = idx - cr * M2;
+      int c = cr / nrows, rr = cr - c * nrows;
+      X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)c * M + (int64_t)row_of(rr) * M2 + k2));
+    }
   }
   if (TW_LDS) load_table<T, M2, NT>(twl, a.twP2);
   const int nunits = (k1 == 0) ? M2 / 2 + 1 : (nrows == 1 ? M2 / 2 : M2);
@@ -543,22 +567,28 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
   // and measured 7% slower.
   const bool split = !LEAN && M2 < 2048 && u <= kRowRegCols;
   cplx<T> wkh[CPT], wkl[CPT];   // w_L^k of this thread's combine units (two table halves)
-#pragma unroll
-  for (int i = 0; i < CPT; ++i) {
-    int unit = split ? (tid + i * NT) >> 1 : tid + i * NT;
-    int64_t e = k1 + (int64_t)M1 * unit;
-    wkh[i] = unit < nunits ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
-    wkl[i] = unit < nunits ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
-  }
   cplx<T> wvh[VPT], wvl[VPT];   // w_M^(j2 row) of this thread's outputs (conjugated at use)
+  auto load_twiddles = [&]() {
 #pragma unroll
-  for (int i = 0; i < VPT; ++i) {
-    int idx = tid + i * NT;
-    int rr = idx / M2, j2 = idx - rr * M2;
-    int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) & (a.L - 1);
-    wvh[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
-    wvl[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
-  }
+    for (int i = 0; i < CPT; ++i) {
+      int unit = split ? (tid + i * NT) >> 1 : tid + i * NT;
+      int64_t e = k1 + (int64_t)M1 * unit;
+      wkh[i] = unit < nunits ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
+      wkl[i] = unit < nunits ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
+    }
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      // wavefront transforms: wavefront rr stores row rr, lane l value e is j2 = l + 64 e
+      int idx = WAVE ? wave * M2 + lane + 64 * i : tid + i * NT;
+      int rr = idx / M2, j2 = idx - rr * M2;
+      int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) & (a.L - 1);
+      wvh[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
+      wvl[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
+    }
+  };
+  // wavefront transforms hold their rows in registers meanwhile: their twiddles
+  // are requested after the forward transforms
+  if constexpr (!WAVE) load_twiddles();
   for (int i = tid; i < sd.ntab; i += NT) tab[i] = ldg(sd.tab + i);
   for (int i = tid; i < Tp + sd.Tq; i += NT) coef[i] = ldg(sd.coef + i);
   if (k1 == 0) {   // partial dots of the column pass -> per-wave sums
@@ -571,7 +601,27 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
     }
   }
   lds_barrier();
-  fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, u * nrows, tw);
+  if constexpr (WAVE) {
+    // each job's row is transformed in registers, with the row's own LDS
+    // region as exchange space, and lands there in natural order
+    for (int j = wave; j < njobs; j += NWAVE) {
+      fft_wave<T, M2, -1>(vcur, X + (size_t)j * STR, tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) X[(size_t)j * STR + lds_pad(lane + 64 * e)] = cnorm(vcur[e]);
+      // (the next row always arrives in the second register set: reloading the
+      // current set in place at the end of the loop body was miscompiled at
+      // -O3 for this target, which clobbered the first stage's inputs)
+      if (j + NWAVE < njobs) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) vcur[e] = vnext[e];
+        if (j + 2 * NWAVE < njobs) load_job(j + 2 * NWAVE, vnext);
+      }
+    }
+    load_twiddles();
+    lds_barrier();
+  } else {
+    fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, u * nrows, tw);
+  }
 
   // bins k = k1 + M1*iA and M - k, spectra of the real inputs, their weighted
   // products, and the even/odd packing of the real inverse; the gain-term
@@ -716,15 +766,27 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
     }
   }
   lds_barrier();
-  fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T>::value>(X, nrows, tw);
-
   cplx<T>* V = (cplx<T>*)sd.V;
+  if constexpr (WAVE) {
+    if (wave < nrows) {   // wavefront rr: inverse of row rr in registers, stored from them
+      cplx<T> y[E];
 #pragma unroll
-  for (int i = 0; i < VPT; ++i) {
-    int idx = tid + i * NT;
-    if (idx < nrows * M2) {
-      int rr = idx / M2, j2 = idx - rr * M2;
-      stg(V + ((int64_t)row_of(rr) * M2 + j2), cnorm(cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i]))));
+      for (int e = 0; e < E; ++e) y[e] = X[(size_t)wave * STR + lds_pad(lane + 64 * e)];
+      __builtin_amdgcn_wave_barrier();
+      fft_wave<T, M2, +1>(y, X + (size_t)wave * STR, tw);
+      cplx<T>* dst = V + (int64_t)row_of(wave) * M2 + lane;
+#pragma unroll
+      for (int e = 0; e < E; ++e) stg(dst + 64 * e, cnorm(cmulc(y[e], cmul(wvh[e], wvl[e]))));
+    }
+  } else {
+    fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T>::value>(X, nrows, tw);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      int idx = tid + i * NT;
+      if (idx < nrows * M2) {
+        int rr = idx / M2, j2 = idx - rr * M2;
+        stg(V + ((int64_t)row_of(rr) * M2 + j2), cnorm(cmulc(X[rr * STR + lds_pad(j2)], cmul(wvh[i], wvl[i]))));
+      }
     }
   }
 
@@ -990,29 +1052,55 @@ hipError_t launch_zero(double* x, int64_t total, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Moments M0 = sum n, M1 = sum k n, and a non-finite count (binary64).
 // ---------------------------------------------------------------------------
+// Compensated binary64 accumulation (Neumaier's variant of Kahan summation,
+// with Knuth's TwoSum for the rounding error of each addition): s + c carries
+// the sum with an error of about one rounding of the result, independent of
+// the number of terms.
+__device__ __forceinline__ void comp_add(double& s, double& c, double x) {
+#pragma clang fp contract(off)
+  const double t = s + x;
+  const double bb = t - s;
+  c += (s - (t - bb)) + (x - bb);
+  s = t;
+}
+
+// Moments of a batch of states: per block the compensated sums of n_k and of
+// k n_k (the product's rounding error, from an FMA, is added as a term of its
+// own) and the count of non-finite values.  part[5b..5b+4] = (M0 sum, M0
+// compensation, M1 sum, M1 compensation, non-finite count).
 __global__ __launch_bounds__(kThreads) void moments_kernel(const double* n, int64_t total, int64_t N,
                                                           double* part) {
-  __shared__ double r0[kThreads], r1[kThreads], r2[kThreads];
-  double a0 = 0, a1 = 0, a2 = 0;
+  // no contraction: the product k n_k must be the rounded one that the
+  // compensated sum adds, its rounding error being added separately
+#pragma clang fp contract(off)
+  __shared__ double r[5][kThreads];
+  double s0 = 0, c0 = 0, s1 = 0, c1 = 0, bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * kThreads) {
-    double v = n[i];
-    if (!isfinite(v)) { a2 += 1.0; continue; }
-    a0 += v;
-    a1 += (double)(i % N + 1) * v;
+    const double v = n[i];
+    if (!isfinite(v)) { bad += 1.0; continue; }
+    comp_add(s0, c0, v);
+    const double k = (double)(i % N + 1);
+    const double pr = k * v;
+    comp_add(s1, c1, pr);
+    c1 += __builtin_fma(k, v, -pr);
   }
-  int tid = threadIdx.x;
-  r0[tid] = a0; r1[tid] = a1; r2[tid] = a2;
+  const int tid = threadIdx.x;
+  r[0][tid] = s0; r[1][tid] = c0; r[2][tid] = s1; r[3][tid] = c1; r[4][tid] = bad;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) { r0[tid] += r0[tid + w]; r1[tid] += r1[tid + w]; r2[tid] += r2[tid + w]; }
+    if (tid < w) {
+      double a = r[0][tid], ca = r[1][tid] + r[1][tid + w];
+      comp_add(a, ca, r[0][tid + w]);
+      r[0][tid] = a; r[1][tid] = ca;
+      double b = r[2][tid], cb = r[3][tid] + r[3][tid + w];
+      comp_add(b, cb, r[2][tid + w]);
+      r[2][tid] = b; r[3][tid] = cb;
+      r[4][tid] += r[4][tid + w];
+    }
     __syncthreads();
   }
-  if (tid == 0) {
-    part[3 * blockIdx.x] = r0[0];
-    part[3 * blockIdx.x + 1] = r1[0];
-    part[3 * blockIdx.x + 2] = r2[0];
-  }
+  if (tid < 5) part[5 * blockIdx.x + tid] = r[tid][0];
 }
 
 // ---------------------------------------------------------------------------

@@ -488,3 +488,32 @@ def test_c2_whole_solve_vs_oracle_trajectory(prec):
     say(f"  n(t_end) err {e:.3e}, M0 {m0:.2e}, M1 {m1:.2e}")
     tol = {"fp64": 1e-10, "fp32c": 1e-10, "fp32": 1e-4}[prec]
     assert e <= tol and m0 <= tol and m1 <= tol
+
+
+def test_solve_moments_are_compensated():
+    """agg_solve's binary64 moments M0 = sum n_k and M1 = sum k n_k carry a
+    compensated sum: on a state whose plain running sum loses many digits to
+    cancellation (large values of both signs around small ones) they agree
+    with the exact rational sums to a few roundings of the result."""
+    from fractions import Fraction
+    N, B = 20000, 3
+    rng = np.random.default_rng(11)
+    big = rng.uniform(1e9, 1e10, size=(B, N // 2))
+    n = np.empty((B, N))
+    n[:, 0::2] = big + rng.uniform(0, 1, size=big.shape)
+    n[:, 1::2] = -big + rng.uniform(0, 1, size=big.shape)
+    k = synth.kernel_constant(2, N)
+    plan = agg.Plan(2, N, k, "fp64", batch=B)
+    nt = torch.tensor(n.reshape(-1), dtype=torch.float64, device=DEV)
+    st = plan.solve(nt, 1e-3, 0.0)
+    torch.cuda.synchronize()
+    plan.close()
+    flat = n.reshape(-1)
+    m0 = sum(Fraction(v) for v in flat)
+    m1 = sum(Fraction(int(i % N + 1)) * Fraction(v) for i, v in enumerate(flat))
+    e0 = abs(Fraction(st.m0_final) - m0) / abs(m0)
+    e1 = abs(Fraction(st.m1_final) - m1) / abs(m1)
+    naive = abs(Fraction(float(np.sum(flat))) - m0) / abs(m0)
+    say(f"  moments vs exact: M0 {float(e0):.2e}, M1 {float(e1):.2e} (numpy pairwise sum M0 {float(naive):.2e})")
+    assert st.steps == 0 and st.m0_final == st.m0_initial
+    assert float(e0) <= 4e-16 and float(e1) <= 4e-16
