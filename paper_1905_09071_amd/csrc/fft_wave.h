@@ -86,4 +86,20 @@ __device__ __forceinline__ void fft_wave(cplx<T> (&v)[P / 64], cplx<T>* scr, con
   fft_wave_stages<T, P, P / 64, 1, DIR>(v, scr, tw);
 }
 
+// The same transform for a sequence held in LDS at lds_pad positions of the
+// region reg (natural order in and out): read lane-major, transformed in
+// registers with reg as exchange space, written back renormalised.  The
+// region must be visible to the wavefront (a barrier after other wavefronts
+// wrote it); other wavefronts must not touch it until a barrier follows.
+template <class T, int P, int DIR>
+__device__ __forceinline__ void fft_wave_lds(cplx<T>* reg, const cplx<T>* __restrict__ tw) {
+  cplx<T> v[P / 64];
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < P / 64; ++e) v[e] = reg[lds_pad(lane + 64 * e)];
+  fft_wave<T, P, DIR>(v, reg, tw);
+#pragma unroll
+  for (int e = 0; e < P / 64; ++e) reg[lds_pad(lane + 64 * e)] = cnorm(v[e]);
+}
+
 }  // namespace agg

@@ -200,6 +200,12 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   cplx<T>* buf = tw + M1;
   cplx<T>* alt = buf + (size_t)a.ub * GMAX * STR;
   __shared__ double red[NWAVE][kColBatch];
+  // launches that fill the GPU, columns of 256 and 512 values: each transform
+  // is held by one wavefront in registers (fft_wave.h), the wavefronts taking
+  // the columns of a group in turn; smaller launches keep the workgroup-wide
+  // stages, whose several wavefronts per transform give shorter chains
+  constexpr bool CWAVE = LEAN && (M1 == 256 || M1 == 512);
+  const int wave_u = uniform_int(threadIdx.x >> 6);
 
   const int M2 = a.M2, g = a.g, lgg = a.lgg;
   const int ngroups = M2 >> lgg;
@@ -293,8 +299,14 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   if (inv) {
     lds_barrier();
     cplx<T>* ib = buf;   // inverse transforms' result
-    if constexpr (!kColPingPong<T, M1, LEAN>) fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, g, tw);
-    else ib = fft_batch_pp<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, alt, g, tw);
+    if constexpr (CWAVE) {
+      for (int q = wave_u; q < g; q += NWAVE) fft_wave_lds<T, M1, +1>(buf + (size_t)q * STR, tw);
+      lds_barrier();
+    } else if constexpr (!kColPingPong<T, M1, LEAN>) {
+      fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, g, tw);
+    } else {
+      ib = fft_batch_pp<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, alt, g, tw);
+    }
 
     // loss weight g_k = sum_c U_c(k) G_c
     double gk[IPT][2];
@@ -381,7 +393,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   // weighting writes them directly and the transform starts at its second stage.
   constexpr int R1 = StageRadix<T>::value < M1 ? StageRadix<T>::value : M1;
   const int64_t rest = N - 2 * (int64_t)j2_0;
-  const bool prune = kColPrune<T, LEAN> && (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
+  const bool prune = kColPrune<T, LEAN> && !CWAVE && (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
   auto put = [&](int slot, int j1, cplx<T> v) {
     if (prune) {
       if (j1 < M1 / R1) {
@@ -445,7 +457,10 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     constexpr int FNB = LEAN ? GMAX : GMAX * (M1 >= 2048 ? 2 : kColBatch);
     constexpr int RF = StageRadix<T>::value;
     cplx<T>* fb = buf;   // forward transforms' result
-    if constexpr (!kColPingPong<T, M1, LEAN>) {
+    if constexpr (CWAVE) {
+      for (int q = wave_u; q < nc * g; q += NWAVE) fft_wave_lds<T, M1, -1>(buf + (size_t)q * STR, tw);
+      lds_barrier();
+    } else if constexpr (!kColPingPong<T, M1, LEAN>) {
       if (prune) fft_batch<T, M1, -1, FNB, STR, NT, RF, R1>(buf, nc * g, tw);
       else fft_batch<T, M1, -1, FNB, STR, NT, RF>(buf, nc * g, tw);
     } else {
@@ -1177,8 +1192,10 @@ int col_batch(int prec, int M1, int u, int nworkgroups) {
   if (ub > kColBatch) ub = kColBatch;
   if (ub > u) ub = u < 1 ? 1 : u;
   // a launch that already fills the GPU gains more from occupancy (small LDS
-  // per workgroup) than from transforming several columns per workgroup
-  if (nworkgroups >= kLeanWorkgroups) ub = 1;
+  // per workgroup) than from transforming several columns per workgroup,
+  // except where its wavefronts transform one column each (columns of 256 and
+  // 512 values): there a group of several columns keeps them all busy
+  if (nworkgroups >= kLeanWorkgroups && !(lean && (M1 == 256 || M1 == 512))) ub = 1;
   return (int)ub;
 }
 
