@@ -33,12 +33,13 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <class T, int P, int E, int NS, int DIR>
+template <class T, int P, int E, int NS, int DIR, int RMAX>
 __device__ __forceinline__ void fft_wave_stages(cplx<T> (&v)[E], cplx<T>* scr, const cplx<T>* __restrict__ tw) {
-  static_assert(E == 2 || E == 4 || E == 8, "radix of the in-register stages");
+  static_assert(E == 2 || E == 4 || E == 8, "values per lane");
+  static_assert(RMAX <= E && E % RMAX == 0, "the largest radix divides the values per lane");
   if constexpr (NS < P) {
     constexpr int REM = P / NS;
-    constexpr int R = REM >= E ? E : REM;   // radix of this stage (divides E)
+    constexpr int R = REM >= RMAX ? RMAX : REM;   // radix of this stage (divides E)
     constexpr int Q = E / R;                // butterflies per lane
     constexpr bool LAST = NS * R == P;
     const int lane = threadIdx.x & 63;
@@ -55,8 +56,10 @@ __device__ __forceinline__ void fft_wave_stages(cplx<T> (&v)[E], cplx<T>* scr, c
       }
       dftR<T, R, DIR>(x);
       if constexpr (LAST) {
+        // renormalised like every stage output of fft_lds.h, so that both
+        // formulations give the same values
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q + r * Q] = x[r];
+        for (int r = 0; r < R; ++r) v[q + r * Q] = cnorm(x[r]);
       } else {
         const int base = (b / NS) * NS * R + j;
 #pragma unroll
@@ -70,20 +73,22 @@ __device__ __forceinline__ void fft_wave_stages(cplx<T> (&v)[E], cplx<T>* scr, c
       // the next stage's writes must not overtake these reads (same wavefront:
       // LDS order is issue order; this only pins the compiler's order)
       __builtin_amdgcn_wave_barrier();
-      fft_wave_stages<T, P, E, NS * R, DIR>(v, scr, tw);
+      fft_wave_stages<T, P, E, NS * R, DIR, RMAX>(v, scr, tw);
     }
   }
 }
 
-// Transforms the lane-major sequence in v (length P = 64 E) in place.
+// Transforms the lane-major sequence in v (length P = 64 E) in place, with the
+// stage sequence of fft_batch<..., RMAX> (radix RMAX while at least RMAX
+// remains, then the rest): the same operations on the same values, so the
+// result is bit for bit that of fft_lds.h.  RMAX must divide E.
 // scr: this wavefront's region of lds_len(P) values (LDS); tw[e] = w_P^e, e < P
 // (any memory the wavefront can read; LDS in the kernels).  DIR = -1 forward,
-// +1 the unnormalised inverse.  Results are not renormalised (float-float):
-// the caller renormalises what it stores.
-template <class T, int P, int DIR>
+// +1 the unnormalised inverse.
+template <class T, int P, int DIR, int RMAX = P / 64>
 __device__ __forceinline__ void fft_wave(cplx<T> (&v)[P / 64], cplx<T>* scr, const cplx<T>* __restrict__ tw) {
   static_assert(P >= 128 && P <= 512 && (P & (P - 1)) == 0, "2 to 8 values per lane");
-  fft_wave_stages<T, P, P / 64, 1, DIR>(v, scr, tw);
+  fft_wave_stages<T, P, P / 64, 1, DIR, RMAX>(v, scr, tw);
 }
 
 // The same transform for a sequence held in LDS at lds_pad positions of the
@@ -91,15 +96,15 @@ __device__ __forceinline__ void fft_wave(cplx<T> (&v)[P / 64], cplx<T>* scr, con
 // registers with reg as exchange space, written back renormalised.  The
 // region must be visible to the wavefront (a barrier after other wavefronts
 // wrote it); other wavefronts must not touch it until a barrier follows.
-template <class T, int P, int DIR>
+template <class T, int P, int DIR, int RMAX = P / 64>
 __device__ __forceinline__ void fft_wave_lds(cplx<T>* reg, const cplx<T>* __restrict__ tw) {
   cplx<T> v[P / 64];
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int e = 0; e < P / 64; ++e) v[e] = reg[lds_pad(lane + 64 * e)];
-  fft_wave<T, P, DIR>(v, reg, tw);
+  fft_wave<T, P, DIR, RMAX>(v, reg, tw);
 #pragma unroll
-  for (int e = 0; e < P / 64; ++e) reg[lds_pad(lane + 64 * e)] = cnorm(v[e]);
+  for (int e = 0; e < P / 64; ++e) reg[lds_pad(lane + 64 * e)] = v[e];
 }
 
 }  // namespace agg

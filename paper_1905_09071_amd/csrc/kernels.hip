@@ -26,8 +26,16 @@ namespace agg {
 // Largest radix of the in-LDS transform stages: radix 4 for float-float (its
 // long arithmetic chains favour more, shorter butterflies), radix 8 otherwise
 // (fewer LDS passes).  Measured on the D=4, N=65536 workload.
-template <class T> struct StageRadix { static constexpr int value = 8; };
-template <> struct StageRadix<ff> { static constexpr int value = 4; };
+template <class T> struct StageRadixBase { static constexpr int value = 8; };
+template <> struct StageRadixBase<ff> { static constexpr int value = 4; };
+// Every variant of a pass (workgroup-wide LDS stages or one transform per
+// wavefront, lean or full) runs the same stage sequence for a given length, so
+// a state's result does not depend on which variant a launch picked (a slot
+// served in a mix computes exactly what it computes alone).  A wavefront holds
+// 256 values as 4 per lane, so its stages are at most radix 4 at that length.
+template <class T, int P> struct StageRadix {
+  static constexpr int value = (P == 256 && StageRadixBase<T>::value > 4) ? 4 : StageRadixBase<T>::value;
+};
 
 // Loads and stores of device memory through global-address-space pointers.
 // Pointers taken from descriptors and launch structs would otherwise compile
@@ -300,12 +308,12 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     lds_barrier();
     cplx<T>* ib = buf;   // inverse transforms' result
     if constexpr (CWAVE) {
-      for (int q = wave_u; q < g; q += NWAVE) fft_wave_lds<T, M1, +1>(buf + (size_t)q * STR, tw);
+      for (int q = wave_u; q < g; q += NWAVE) fft_wave_lds<T, M1, +1, StageRadix<T, M1>::value>(buf + (size_t)q * STR, tw);
       lds_barrier();
     } else if constexpr (!kColPingPong<T, M1, LEAN>) {
-      fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, g, tw);
+      fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T, M1>::value>(buf, g, tw);
     } else {
-      ib = fft_batch_pp<T, M1, +1, GMAX, STR, NT, StageRadix<T>::value>(buf, alt, g, tw);
+      ib = fft_batch_pp<T, M1, +1, GMAX, STR, NT, StageRadix<T, M1>::value>(buf, alt, g, tw);
     }
 
     // loss weight g_k = sum_c U_c(k) G_c
@@ -391,7 +399,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   // of the group's columns lies in the first block of the first radix-R1 stage
   // (j1 < M1/R1), that stage only copies each input to its R1 outputs: the
   // weighting writes them directly and the transform starts at its second stage.
-  constexpr int R1 = StageRadix<T>::value < M1 ? StageRadix<T>::value : M1;
+  constexpr int R1 = StageRadix<T, M1>::value < M1 ? StageRadix<T, M1>::value : M1;
   const int64_t rest = N - 2 * (int64_t)j2_0;
   const bool prune = kColPrune<T, LEAN> && !CWAVE && (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
   auto put = [&](int slot, int j1, cplx<T> v) {
@@ -455,10 +463,10 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
     // lean launches transform one column per pass (ub = 1): one group of columns per register pass
     constexpr int FNB = LEAN ? GMAX : GMAX * (M1 >= 2048 ? 2 : kColBatch);
-    constexpr int RF = StageRadix<T>::value;
+    constexpr int RF = StageRadix<T, M1>::value;
     cplx<T>* fb = buf;   // forward transforms' result
     if constexpr (CWAVE) {
-      for (int q = wave_u; q < nc * g; q += NWAVE) fft_wave_lds<T, M1, -1>(buf + (size_t)q * STR, tw);
+      for (int q = wave_u; q < nc * g; q += NWAVE) fft_wave_lds<T, M1, -1, StageRadix<T, M1>::value>(buf + (size_t)q * STR, tw);
       lds_barrier();
     } else if constexpr (!kColPingPong<T, M1, LEAN>) {
       if (prune) fft_batch<T, M1, -1, FNB, STR, NT, RF, R1>(buf, nc * g, tw);
@@ -620,9 +628,9 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
     // each job's row is transformed in registers, with the row's own LDS
     // region as exchange space, and lands there in natural order
     for (int j = wave; j < njobs; j += NWAVE) {
-      fft_wave<T, M2, -1>(vcur, X + (size_t)j * STR, tw);
+      fft_wave<T, M2, -1, StageRadix<T, M2>::value>(vcur, X + (size_t)j * STR, tw);
 #pragma unroll
-      for (int e = 0; e < E; ++e) X[(size_t)j * STR + lds_pad(lane + 64 * e)] = cnorm(vcur[e]);
+      for (int e = 0; e < E; ++e) X[(size_t)j * STR + lds_pad(lane + 64 * e)] = vcur[e];
       // (the next row always arrives in the second register set: reloading the
       // current set in place at the end of the loop body was miscompiled at
       // -O3 for this target, which clobbered the first stage's inputs)
@@ -635,7 +643,7 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
     load_twiddles();
     lds_barrier();
   } else {
-    fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, u * nrows, tw);
+    fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T, M2>::value>(X, u * nrows, tw);
   }
 
   // bins k = k1 + M1*iA and M - k, spectra of the real inputs, their weighted
@@ -704,7 +712,7 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
         if (valid && c < u) {
           cplx<T> xa, xb;
           unpack(c, iA, iB, rB, zero_bin, self, wk, xa, xb);
-          x[c] = side ? xb : xa;
+          x[c] = cnorm(side ? xb : xa);   // as stored by the LDS mapping
         }
       }
       // running product over the ids of each term (continued from the
@@ -788,13 +796,13 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
 #pragma unroll
       for (int e = 0; e < E; ++e) y[e] = X[(size_t)wave * STR + lds_pad(lane + 64 * e)];
       __builtin_amdgcn_wave_barrier();
-      fft_wave<T, M2, +1>(y, X + (size_t)wave * STR, tw);
+      fft_wave<T, M2, +1, StageRadix<T, M2>::value>(y, X + (size_t)wave * STR, tw);
       cplx<T>* dst = V + (int64_t)row_of(wave) * M2 + lane;
 #pragma unroll
       for (int e = 0; e < E; ++e) stg(dst + 64 * e, cnorm(cmulc(y[e], cmul(wvh[e], wvl[e]))));
     }
   } else {
-    fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T>::value>(X, nrows, tw);
+    fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T, M2>::value>(X, nrows, tw);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       int idx = tid + i * NT;
@@ -927,7 +935,7 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
       X[cr * STR + lds_pad(k2)] = ldg(Z1 + ((size_t)gc * M + (int64_t)row_of(rr) * M2 + k2));
     }
     lds_barrier();
-    fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T>::value>(X, nc * nrows, tw);
+    fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T, M2>::value>(X, nc * nrows, tw);
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
       const int unit = tid + i * NT;
@@ -995,7 +1003,7 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
     }
   }
   lds_barrier();
-  fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T>::value>(X, nrows, tw);
+  fft_batch<T, M2, +1, NB, STR, NT, StageRadix<T, M2>::value>(X, nrows, tw);
 
   cplx<T>* V = (cplx<T>*)sd.V;
 #pragma unroll

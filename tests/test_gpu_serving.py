@@ -105,6 +105,40 @@ def test_mixed_requests_equal_alone(prec):
         assert st.t_submit <= st.t_admit <= st.t_finish
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_saturating_mix_equals_alone(prec):
+    """Enough concurrent requests of one transform length that the bucket's
+    launches take the variants for launches that fill the GPU (several
+    workgroups per CU, one transform per wavefront), while each request served
+    alone takes the full variants: every result is still bit for bit the alone
+    one (all variants run the same stage sequence with the same rounding), and
+    within the parity bar of the oracle."""
+    N = 65536
+    reqs = []
+    for i in range(14):
+        D = 2 if i < 8 else 4          # L = 2^17 (M1 = M2 = 256) and 2^18 (M1 = 512, M2 = 256)
+        a = 0.15 + 0.05 * i
+        dt = min(1e-3, 1.0 / (D * D * N ** a))
+        reqs.append(dict(D=D, N=N, a=a, kernel=synth.kernel_ballistic(D, N, a),
+                         n0=synth.n0_uniform_head(N, 100 + i, 16), dt=dt, t_end=3 * dt))
+    eng = agg.Engine(0)
+    tickets = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in reqs]
+    res = drain(eng, tickets, [r["N"] for r in reqs])
+    eng.close()
+    for i, (r, t) in enumerate(zip(reqs, tickets)):
+        rc, out, st = res[t]
+        assert rc == agg.AGG_OK
+        solo = served_alone(r, prec)
+        same = np.array_equal(out, solo)
+        say(f"[serve-mix] D={r['D']} a={r['a']:.2f} steps={st.steps} equal alone: {same}, "
+            f"max diff {np.max(np.abs(out - solo)):.3e}")
+        assert same
+        if i in (0, 9):
+            eo = vs_oracle(out, r)
+            say(f"  rel err vs oracle {eo:.3e}")
+            assert eo <= TOL[prec]
+
+
 def test_budget_and_errors():
     N = 4096
     k = synth.kernel_ballistic(3, N, 0.5)
