@@ -3,8 +3,10 @@
     python -m paper_1905_09071_amd.build        # or __graft_entry__.build()
 
 Every HIP source is compiled with packed-FP32 instruction selection disabled
-(-mno-packed-fp32-ops equivalent via -target-feature) and without fast-math, so
-the float-float error-free transforms keep their exact rounding behaviour.
+(-mno-packed-fp32-ops equivalent via -target-feature), without fast-math and
+without automatic FMA contraction (the fused multiply-adds are explicit), so
+the float-float error-free transforms keep their exact rounding behaviour and
+every kernel variant rounds the same expression the same way.
 """
 from __future__ import annotations
 
@@ -23,7 +25,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-fno-fast-math", "-ffp-contract=fast-honor-pragmas"]
+          "-packed-fp32-ops", "-fno-fast-math", "-ffp-contract=off"]
 SOURCES = [
     ("kernels.hip", True),
     ("noalloc.hip", True),

@@ -9,10 +9,11 @@
 //
 // Build note: everything here relies on IEEE round-to-nearest, no flush of
 // binary32 subnormals, and no reassociation (never compile with fast-math).
-// Contraction of a multiply and an add into one FMA is switched off inside
-// every float-float operation: fusing TwoProd's rounded product with the
-// following Fast2Sum (legal under -ffp-contract=fast once inlined) would
-// destroy the error terms.
+// The library is built with -ffp-contract=off: a multiply and an add are fused
+// only where the source says so (__builtin_fma).  Besides keeping the
+// float-float error-free transforms exact (fusing TwoProd's rounded product
+// with a following Fast2Sum would destroy the error terms), this makes every
+// expression round the same way in every kernel variant that inlines it.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -108,6 +109,23 @@ template <class T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
 // a * conj(b)
 template <class T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
   return cplx<T>{a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// Native formats: one product and one fused multiply-add per part, written
+// out.  The library is compiled without automatic contraction, so every
+// kernel variant rounds a given expression the same way (a state's result
+// does not depend on which variant a launch used); the fused forms that matter
+// are explicit.
+__device__ __forceinline__ cplx<double> cmul(cplx<double> a, cplx<double> b) {
+  return cplx<double>{__builtin_fma(a.re, b.re, -(a.im * b.im)), __builtin_fma(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplx<double> cmulc(cplx<double> a, cplx<double> b) {
+  return cplx<double>{__builtin_fma(a.re, b.re, a.im * b.im), __builtin_fma(a.im, b.re, -(a.re * b.im))};
+}
+__device__ __forceinline__ cplx<float> cmul(cplx<float> a, cplx<float> b) {
+  return cplx<float>{__builtin_fmaf(a.re, b.re, -(a.im * b.im)), __builtin_fmaf(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplx<float> cmulc(cplx<float> a, cplx<float> b) {
+  return cplx<float>{__builtin_fmaf(a.re, b.re, a.im * b.im), __builtin_fmaf(a.im, b.re, -(a.re * b.im))};
 }
 template <class T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cplx<T>{a.re, -a.im}; }
 template <class T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {

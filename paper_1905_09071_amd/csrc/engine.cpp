@@ -4,28 +4,35 @@
 // its own state, Heun buffers, spectra and tables in device memory, admitted in
 // FIFO order while its footprint fits in the free budget.  Running slots whose
 // plans share the launch geometry (L, M1, M2, g, precision, row-pass chunk
-// capacity) form a bucket; at every tick each bucket gets ONE row launch and
-// ONE column launch over all of its slots, with each slot's stage (first
-// forward pass, Heun stage 1, Heun stage 2, last stage) carried in its device
-// descriptor.  A slot therefore
-// computes exactly what it would compute alone: nothing in a slot's arithmetic
-// depends on its neighbours.  Requests that arrive while others run join at
-// the next tick; finished slots are copied out and their memory returned.
-// Buckets are independent within a tick, so with several buckets each one runs
-// on one of a few lane streams (forked from and joined back into the
-// scheduler's stream), letting small launches of different lengths share the
-// GPU instead of queueing behind each other.
+// capacity) form a bucket.  A tick gives every bucket ONE row launch and ONE
+// column launch over all of its slots, then advances a tick counter in device
+// memory; each slot's stage (first forward pass, Heun stage 1 or 2 of a step,
+// done) follows on the device from that counter and the tick at which the slot
+// started, so a slot computes exactly what it would compute alone: nothing in
+// its arithmetic depends on its neighbours (every launch variant runs the same
+// stage sequence).
+//
+// The ticks are replayed from a captured hipGraph (several ticks per graph
+// launch).  The launches read their bucket's slot table and its list of active
+// entries from device memory, with a grid sized for a power-of-two capacity
+// (workgroups past the active list exit at once), so admissions and
+// retirements only rewrite that list between graph launches: the graph is
+// captured again only when the set of buckets, a bucket's capacity or its
+// table maxima change.  With several buckets each one runs on one of a few
+// lane streams (forked from and joined back into the scheduler's stream inside
+// the graph), letting small launches of different lengths share the GPU.
 //
 // Memory: the engine owns one device region (its budget) and one pinned host
 // region, each carved by a first-fit allocator.  A request holds one
 // contiguous device block (tables, state, Heun vectors, spectra) and one
-// pinned host block (tables and initial state staged for upload, then the
-// result).  The tables are built and staged by the submitting thread; at
-// admission the scheduler enqueues a single asynchronous copy on its stream,
-// ordered before the request's first launch.  Admission therefore allocates
-// nothing from the runtime and never waits on the device.
+// pinned host block (tables and initial state staged for upload, its slot
+// descriptor, then the result).  The tables are built and staged by the
+// submitting thread; at admission the scheduler enqueues the asynchronous
+// copies on its stream, ordered before the request's first launch.  Admission
+// therefore allocates nothing from the runtime and never waits on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -94,10 +101,10 @@ struct Pool {
 // Byte offsets inside a request's device block:
 //   [tables | n | k1 | n~ | G | dots | V | Z1]
 // The host block mirrors [tables | n] for the single upload, then holds the
-// result.
+// slot descriptor (uploaded into the bucket's table) and the result.
 struct ReqLayout {
   size_t o_n = 0, o_k1 = 0, o_nt = 0, o_G = 0, o_dots = 0, o_V = 0, o_Z1 = 0, dev_total = 0;
-  size_t upload = 0, o_out = 0, host_total = 0;
+  size_t upload = 0, o_desc = 0, o_out = 0, host_total = 0;
 };
 
 static ReqLayout request_layout(const PlanTables& T, size_t image_bytes) {
@@ -114,7 +121,8 @@ static ReqLayout request_layout(const PlanTables& T, size_t image_bytes) {
   l.o_Z1 = off; off = align256(off + (size_t)T.u * T.M * cs);
   l.dev_total = off;
   l.upload = l.o_n + nb;
-  l.o_out = align256(l.upload);
+  l.o_desc = align256(l.upload);
+  l.o_out = align256(l.o_desc + sizeof(SlotDesc));
   l.host_total = l.o_out + nb;
   return l;
 }
@@ -136,16 +144,39 @@ struct Request {
   SlotDesc sd;
   const double* h_out = nullptr;    // pinned result buffer (inside the host block)
   hipEvent_t done_ev = nullptr;
-  int64_t stage = 0;                // 0: forward pass pending; 2s+1: stage 1 of step s; 2s+2: stage 2
+  struct Bucket* bucket = nullptr;  // while running
+  int entry = -1;                   // its entry in the bucket's slot table
+  int64_t start_tick = 0;           // tick of its first (forward) pass
   int status = AGG_PENDING;
   std::vector<double> result;
 };
 
 using BucketKey = std::tuple<int64_t, int, int, int, int, int>;   // L, M1, M2, g, prec, chunk cap
 
+// Slots of one launch geometry.  Its device block (from the engine's pool,
+// kept while the engine lives) holds the slot table (max_slots descriptors),
+// two active lists ([count, entries...]; the launches read the current one)
+// and the geometry's twiddle tables (copied from the first member's block, so
+// the captured launches never point into a request's memory).
+struct Bucket {
+  PlanTables geo;                   // launch geometry only (no factor data)
+  size_t dev_off = 0, dev_len = 0;
+  SlotDesc* d_desc = nullptr;
+  int* d_active = nullptr;
+  int* h_active = nullptr;          // pinned staging of the list (engine's host pool)
+  size_t host_off = 0, host_len = 0;
+  hipEvent_t list_ev = nullptr;     // the last list upload
+  void* tw[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<Request*> slot;       // table entry -> member (nullptr: free)
+  std::vector<int> order;           // members' entries in admission order
+  int cap = 0;                      // logical slots of the captured launches
+  int umax = 1, tab_max = 0, coef_max = 0;   // maxima the captured launches were built for
+  bool list_dirty = false;
+};
+
 struct Engine {
   agg_engine_config cfg{};
-  hipStream_t stream = nullptr;      // uploads, descriptors, result copies, single-bucket ticks
+  hipStream_t stream = nullptr;      // uploads, result copies, graph launches
   static constexpr int kLanes = 4;
   hipStream_t lanes[kLanes] = {nullptr};   // bucket launches of multi-bucket ticks
   hipEvent_t fork_ev = nullptr, join_ev[kLanes] = {nullptr};
@@ -170,22 +201,37 @@ struct Engine {
   Pool dev, host;
   int64_t n_staged = 0;
   std::vector<hipEvent_t> spare_events;
-  // descriptor staging ring (pinned host -> device), one entry per tick
-  static constexpr int kRing = 8;
-  SlotDesc* h_desc[kRing] = {nullptr};
-  SlotDesc* d_desc[kRing] = {nullptr};
-  hipEvent_t ring_ev[kRing] = {nullptr};
-  bool ring_used[kRing] = {false};
-  int ring_pos = 0;
   int cap_slots = 256;
+  // ticks
+  std::map<BucketKey, std::unique_ptr<Bucket>> buckets;
+  int64_t* d_tick = nullptr;         // device tick counter (start of the device region)
+  int64_t host_tick = 0;             // ticks enqueued so far
+  static constexpr int kTicksPerGraph = 4;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_stale = true;
+  // replaced graphs, destroyed once the device has passed their last launch
+  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> old_graphs;
+  static constexpr int kInFlight = 2;   // graph launches the host may run ahead
+  hipEvent_t launch_ev[kInFlight] = {nullptr};
+  bool launch_used[kInFlight] = {false};
+  int launch_pos = 0;
+  bool poisoned = false;             // a launch failed: every running request fails
 
   void run();
   void admit();
-  void tick();
+  bool join_bucket(Request& r);
+  bool drop_empty_buckets();
+  void leave_finished();
+  hipError_t upload_lists();
+  hipError_t enqueue_tick();
+  hipError_t rebuild_graph();
+  hipError_t launch_ticks();
+  void collect_graphs(bool all);
   void retire(bool block);
   bool take_host(Request& r);
   bool setup_device(Request& r);
   void release(Request& r);
+  LaunchArgs bucket_args(const Bucket& b) const;
 };
 
 // Gives a request that was staged in pageable memory its pinned block.
@@ -229,6 +275,10 @@ bool Engine::setup_device(Request& r) {
   s.o_pids = r.st.o_pids; s.o_qoff = r.st.o_qoff; s.o_qids = r.st.o_qids; s.o_qkm = r.st.o_qkm; s.o_pfrom = r.st.o_pfrom;
   s.nch = r.st.nch; s.o_chc = r.st.o_chc; s.o_chcols = r.st.o_chcols; s.o_cht = r.st.o_cht;
   s.N = (int)r.tab.N; s.u = r.tab.u; s.Tp = r.st.Tp; s.Tq = r.st.Tq;
+  s.mode = CM_NONE;
+  s.nsteps = r.nsteps;
+  s.dt = r.dt;
+  s.dt_last = r.last_dt;
   if (!spare_events.empty()) {
     r.done_ev = spare_events.back();
     spare_events.pop_back();
@@ -251,6 +301,108 @@ void Engine::release(Request& r) {
   r.done_ev = nullptr;
 }
 
+static int pow2_at_least(int x) {
+  int c = 1;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+// Puts an admitted request into its bucket (created on first use) at the next
+// tick: its descriptor goes to a free table entry (uploaded from its pinned
+// block) and its entry joins the active list.  False if the bucket's block
+// could not be reserved (the request then waits at the head of the queue).
+bool Engine::join_bucket(Request& r) {
+  const PlanTables& T = r.tab;
+  const BucketKey key(T.L, T.M1, T.M2, T.g, T.prec, T.cmax);
+  auto it = buckets.find(key);
+  if (it == buckets.end()) {
+    auto b = std::make_unique<Bucket>();
+    b->geo.prec = T.prec; b->geo.L = T.L; b->geo.M = T.M; b->geo.M1 = T.M1; b->geo.M2 = T.M2;
+    b->geo.g = T.g; b->geo.b = T.b; b->geo.cmax = T.cmax; b->geo.u = T.u; b->geo.N = T.N;
+    const size_t tw_bytes = r.lay.o_n - r.im.o_tw1;   // the four twiddle tables, as laid out in the image
+    const size_t desc_bytes = align256(sizeof(SlotDesc) * (size_t)cap_slots);
+    const size_t list_bytes = align256(sizeof(int) * (size_t)(cap_slots + 1));
+    b->dev_len = desc_bytes + list_bytes + tw_bytes;
+    if (!dev.alloc(b->dev_len, &b->dev_off)) return false;
+    b->host_len = list_bytes;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!host.alloc(b->host_len, &b->host_off)) {
+        dev.release(b->dev_off, b->dev_len);
+        return false;
+      }
+    }
+    char* d = dev_base + b->dev_off;
+    b->d_desc = (SlotDesc*)d;
+    b->d_active = (int*)(d + desc_bytes);
+    char* tw = d + desc_bytes + list_bytes;
+    const size_t o[4] = {r.im.o_tw1, r.im.o_tw2, r.im.o_twlo, r.im.o_twhi};
+    for (int i = 0; i < 4; ++i) b->tw[i] = tw + (o[i] - r.im.o_tw1);
+    b->h_active = (int*)(host_base + b->host_off);
+    b->slot.assign(cap_slots, nullptr);
+    if (hipEventCreateWithFlags(&b->list_ev, hipEventDisableTiming) != hipSuccess) b->list_ev = nullptr;
+    // twiddles from the first member's block, right after its upload (stream order)
+    if (hipMemcpyAsync(tw, dev_base + r.dev_off + r.im.o_tw1, tw_bytes, hipMemcpyDeviceToDevice, stream) !=
+        hipSuccess)
+      r.status = AGG_EHIP;
+    it = buckets.emplace(key, std::move(b)).first;
+  }
+  Bucket& b = *it->second;
+  int entry = -1;
+  for (int i = 0; i < cap_slots && entry < 0; ++i)
+    if (!b.slot[i]) entry = i;
+  if (entry < 0) return false;   // cannot happen: running requests are capped at cap_slots
+  r.bucket = &b;
+  r.entry = entry;
+  r.start_tick = host_tick;
+  r.sd.start_tick = host_tick;
+  SlotDesc* hd = (SlotDesc*)(host_base + r.host_off + r.lay.o_desc);
+  *hd = r.sd;
+  if (hipMemcpyAsync(b.d_desc + entry, hd, sizeof(SlotDesc), hipMemcpyHostToDevice, stream) != hipSuccess)
+    r.status = AGG_EHIP;
+  b.slot[entry] = &r;
+  b.order.push_back(entry);
+  b.list_dirty = true;
+  // the captured launches are rebuilt when the bucket outgrows them
+  const int ntab = r.st.ntab, ncoef = r.st.Tp + r.st.Tq;
+  if (r.tab.u > b.umax || ntab > b.tab_max || ncoef > b.coef_max || pow2_at_least((int)b.order.size()) > b.cap) {
+    b.umax = std::max(b.umax, r.tab.u);
+    b.tab_max = std::max(b.tab_max, ntab);
+    b.coef_max = std::max(b.coef_max, ncoef);
+    graph_stale = true;
+  }
+  return true;
+}
+
+// Frees the blocks of buckets without members (when a new geometry finds no
+// room): waits until the device has finished with them, drops the graph that
+// refers to them.  False if there was nothing to free.
+bool Engine::drop_empty_buckets() {
+  bool any = false;
+  for (auto& kv : buckets) any |= kv.second->order.empty();
+  if (!any) return false;
+  (void)hipStreamSynchronize(stream);
+  for (hipStream_t l : lanes) (void)hipStreamSynchronize(l);
+  if (gexec) {
+    (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+  collect_graphs(true);
+  for (auto it = buckets.begin(); it != buckets.end();) {
+    Bucket& b = *it->second;
+    if (!b.order.empty()) { ++it; continue; }
+    dev.release(b.dev_off, b.dev_len);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      host.release(b.host_off, b.host_len);
+    }
+    if (b.list_ev) (void)hipEventDestroy(b.list_ev);
+    it = buckets.erase(it);
+  }
+  graph_stale = true;
+  return true;
+}
+
 void Engine::admit() {
   for (;;) {
     Request* r;
@@ -260,7 +412,11 @@ void Engine::admit() {
       r = queue.front().get();      // only this thread pops: r stays valid unlocked
       if (!r->ready.load(std::memory_order_acquire)) return;
     }
-    if (r->nsteps > 0 && !setup_device(*r)) return;     // FIFO: no overtaking
+    if (r->nsteps > 0) {
+      if (!r->has_dev && !setup_device(*r)) return;      // FIFO: no overtaking
+      if (r->status == AGG_PENDING && !join_bucket(*r) && !(drop_empty_buckets() && join_bucket(*r)))
+        return;   // keeps its blocks, retries next time
+    }
     std::unique_ptr<Request> rp;
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -270,6 +426,13 @@ void Engine::admit() {
     r->t_admit = now_s();
     if (r->nsteps == 0 || r->status != AGG_PENDING) {   // nothing to integrate, or set-up failed
       if (r->status == AGG_PENDING) r->status = AGG_OK;
+      if (r->bucket) {   // (set-up failed after joining: leave again)
+        Bucket& b = *r->bucket;
+        b.slot[r->entry] = nullptr;
+        b.order.erase(std::find(b.order.begin(), b.order.end(), r->entry));
+        b.list_dirty = true;
+        r->bucket = nullptr;
+      }
       r->t_finish = now_s();
       release(*r);
       std::lock_guard<std::mutex> lk(mu);
@@ -283,93 +446,168 @@ void Engine::admit() {
   }
 }
 
-void Engine::tick() {
-  if (running.empty()) return;
-  int slot_ring = ring_pos;
-  ring_pos = (ring_pos + 1) % kRing;
-  if (ring_used[slot_ring]) (void)hipEventSynchronize(ring_ev[slot_ring]);
-  SlotDesc* hd = h_desc[slot_ring];
-  SlotDesc* dd = d_desc[slot_ring];
-
-  // buckets of equal launch geometry, in admission order
-  std::map<BucketKey, std::vector<Request*>> buckets;
+// Requests whose last stage has been enqueued (tick start + 2 nsteps) leave
+// their bucket; their final state is copied out behind those launches.
+void Engine::leave_finished() {
+  std::vector<std::unique_ptr<Request>> still;
   for (auto& rp : running) {
-    const PlanTables& T = rp->tab;
-    buckets[BucketKey(T.L, T.M1, T.M2, T.g, T.prec, T.cmax)].push_back(rp.get());
-  }
-  struct Launch { int off, cnt, umax, tab_max, coef_max; Request* first; };
-  std::vector<Launch> launches;
-  int base = 0;
-  for (auto& kv : buckets) {
-    Launch L{base, 0, 1, 0, 0, kv.second.front()};
-    for (Request* r : kv.second) {
-      SlotDesc s = r->sd;
-      if (r->stage == 0) {
-        s.mode = CM_FWD; s.row_on = 0; s.dt = 0.0;
-      } else {
-        int64_t step = (r->stage - 1) / 2;
-        bool st1 = (r->stage % 2) == 1;
-        s.row_on = 1;
-        s.dt = step == r->nsteps - 1 ? r->last_dt : r->dt;
-        s.mode = st1 ? CM_H1 : (step == r->nsteps - 1 ? CM_H2 : CM_H2_FWD);
-      }
-      hd[base + L.cnt] = s;
-      L.umax = std::max(L.umax, r->tab.u);
-      L.tab_max = std::max(L.tab_max, r->st.ntab);
-      L.coef_max = std::max(L.coef_max, r->st.Tp + r->st.Tq);
-      ++L.cnt;
+    Request& r = *rp;
+    const bool last = host_tick >= r.start_tick + 2 * r.nsteps + 1 || poisoned;
+    if (!last) {
+      still.push_back(std::move(rp));
+      continue;
     }
-    launches.push_back(L);
-    base += L.cnt;
+    if (poisoned) r.status = AGG_EHIP;
+    Bucket& b = *r.bucket;
+    b.slot[r.entry] = nullptr;
+    b.order.erase(std::find(b.order.begin(), b.order.end(), r.entry));
+    b.list_dirty = true;
+    // shrink the launches once a quarter of their capacity is left (not at
+    // every power of two, which retirements and arrivals cross back and forth)
+    if ((int)b.order.size() * 4 <= b.cap) graph_stale = true;
+    r.bucket = nullptr;
+    (void)hipMemcpyAsync((void*)r.h_out, r.sd.n_state, sizeof(double) * r.tab.N, hipMemcpyDeviceToHost, stream);
+    (void)hipEventRecord(r.done_ev, stream);
+    finishing.push_back(std::move(rp));
   }
-  hipError_t e = hipMemcpyAsync(dd, hd, sizeof(SlotDesc) * base, hipMemcpyHostToDevice, stream);
-  const bool multi = launches.size() > 1;
-  const int nl = multi ? (int)std::min<size_t>(launches.size(), kLanes) : 0;
-  if (multi && e == hipSuccess) e = hipEventRecord(fork_ev, stream);
+  running.swap(still);
+  if (running.empty()) poisoned = false;   // later requests start afresh
+}
+
+// Uploads the active lists that changed (from each bucket's pinned staging,
+// whose previous upload is waited for first: it was enqueued at least one
+// graph launch earlier).
+hipError_t Engine::upload_lists() {
+  hipError_t e = hipSuccess;
+  for (auto& kv : buckets) {
+    Bucket& b = *kv.second;
+    if (!b.list_dirty) continue;
+    if (b.list_ev) (void)hipEventSynchronize(b.list_ev);
+    b.h_active[0] = (int)b.order.size();
+    for (size_t i = 0; i < b.order.size(); ++i) b.h_active[1 + i] = b.order[i];
+    e = hipMemcpyAsync(b.d_active, b.h_active, sizeof(int) * (b.order.size() + 1), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    if (b.list_ev) e = hipEventRecord(b.list_ev, stream);
+    if (e != hipSuccess) return e;
+    b.list_dirty = false;
+  }
+  return e;
+}
+
+LaunchArgs Engine::bucket_args(const Bucket& b) const {
+  SharedTables st;
+  st.twP1 = b.tw[0]; st.twP2 = b.tw[1]; st.twLlo = b.tw[2]; st.twLhi = b.tw[3];
+  LaunchArgs a = base_args(b.geo, st, b.d_desc, b.cap);
+  a.mode = -1;
+  a.active = b.d_active;
+  a.tick = d_tick;
+  a.umax = b.umax;
+  a.tab_max = b.tab_max;
+  a.coef_max = b.coef_max;
+  const int nwg = b.cap * (b.geo.M2 / b.geo.g);
+  a.ub = col_batch(b.geo.prec, b.geo.M1, b.umax, nwg);
+  a.lean = nwg >= kLeanWorkgroups ? 1 : 0;
+  return a;
+}
+
+// One tick: every bucket with members gets its row and column launch (lanes
+// when there are several), then the counter advances.
+hipError_t Engine::enqueue_tick() {
+  std::vector<Bucket*> live;
+  for (auto& kv : buckets)
+    if (kv.second->cap > 0) live.push_back(kv.second.get());
+  hipError_t e = hipSuccess;
+  const bool multi = live.size() > 1;
+  const int nl = multi ? (int)std::min<size_t>(live.size(), kLanes) : 0;
+  if (multi) e = hipEventRecord(fork_ev, stream);
   for (int l = 0; l < nl && e == hipSuccess; ++l) e = hipStreamWaitEvent(lanes[l], fork_ev, 0);
-  for (size_t b = 0; b < launches.size() && e == hipSuccess; ++b) {
-    hipStream_t ls = multi ? lanes[b % kLanes] : stream;
-    const Launch& L = launches[b];
-    const PlanTables& T = L.first->tab;
-    // every slot of a bucket has identical twiddle tables: take the first's
-    LaunchArgs a = base_args(T, L.first->st, dd + L.off, L.cnt);
-    int nwg = L.cnt * (T.M2 / T.g);
-    a.mode = -1;
-    a.umax = L.umax;
-    a.ub = col_batch(T.prec, T.M1, L.umax, nwg);
-    a.lean = nwg >= kLeanWorkgroups ? 1 : 0;
-    a.tab_max = L.tab_max;
-    a.coef_max = L.coef_max;
-    e = launch_row(T.prec, a, ls);
-    if (e == hipSuccess) e = launch_col(T.prec, a, ls);
+  for (size_t i = 0; i < live.size() && e == hipSuccess; ++i) {
+    hipStream_t ls = multi ? lanes[i % kLanes] : stream;
+    const LaunchArgs a = bucket_args(*live[i]);
+    e = launch_row(live[i]->geo.prec, a, ls);
+    if (e == hipSuccess) e = launch_col(live[i]->geo.prec, a, ls);
   }
   for (int l = 0; l < nl && e == hipSuccess; ++l) {
     e = hipEventRecord(join_ev[l], lanes[l]);
     if (e == hipSuccess) e = hipStreamWaitEvent(stream, join_ev[l], 0);
   }
-  if (e == hipSuccess) e = hipEventRecord(ring_ev[slot_ring], stream);
-  ring_used[slot_ring] = true;
-  if (e != hipSuccess) {
-    // a failed launch poisons every running request of this tick
-    for (auto& rp : running) rp->status = AGG_EHIP;
-  }
+  if (e == hipSuccess) e = launch_tick(d_tick, stream);
+  return e;
+}
 
-  // advance stages; requests whose last stage was just enqueued copy out
-  std::vector<std::unique_ptr<Request>> still;
-  for (auto& rp : running) {
-    Request& r = *rp;
-    r.stage++;
-    bool last = r.stage == 2 * r.nsteps + 1 || r.status == AGG_EHIP;
-    if (last) {
-      (void)hipMemcpyAsync((void*)r.h_out, r.sd.n_state, sizeof(double) * r.tab.N, hipMemcpyDeviceToHost,
-                           stream);
-      (void)hipEventRecord(r.done_ev, stream);
-      finishing.push_back(std::move(rp));
-    } else {
-      still.push_back(std::move(rp));
+// New capacities from the members, one tick launched directly (so that every
+// kernel's one-time set-up happens outside a capture), then the graph of
+// kTicksPerGraph ticks captured from the same enqueue.
+hipError_t Engine::rebuild_graph() {
+  if (gexec) {   // its launches may still be in flight: destroyed when they are done
+    hipEvent_t ev = nullptr;
+    if (!spare_events.empty()) {
+      ev = spare_events.back();
+      spare_events.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ev = nullptr;
     }
+    if (ev && hipEventRecord(ev, stream) == hipSuccess) {
+      old_graphs.emplace_back(gexec, ev);
+    } else {
+      (void)hipStreamSynchronize(stream);
+      (void)hipGraphExecDestroy(gexec);
+      if (ev) spare_events.push_back(ev);
+    }
+    gexec = nullptr;
   }
-  running.swap(still);
+  for (auto& kv : buckets) {
+    Bucket& b = *kv.second;
+    b.cap = b.order.empty() ? 0 : pow2_at_least((int)b.order.size());
+  }
+  hipError_t e = enqueue_tick();
+  if (e != hipSuccess) return e;
+  host_tick += 1;
+  hipGraph_t g = nullptr;
+  e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  hipError_t ee = hipSuccess;
+  for (int t = 0; t < kTicksPerGraph && ee == hipSuccess; ++t) ee = enqueue_tick();
+  e = hipStreamEndCapture(stream, &g);
+  if (ee != hipSuccess) e = ee;
+  if (e == hipSuccess) e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  graph_stale = false;
+  return e;
+}
+
+// Enqueues the next ticks: a graph launch, with at most kInFlight of them
+// ahead of the device.
+hipError_t Engine::launch_ticks() {
+  hipError_t e = hipSuccess;
+  if (graph_stale) {
+    e = rebuild_graph();
+    if (e != hipSuccess) return e;
+    return hipSuccess;   // the rebuild ran one tick; the graph starts at the next call
+  }
+  if (launch_used[launch_pos]) (void)hipEventSynchronize(launch_ev[launch_pos]);
+  e = hipGraphLaunch(gexec, stream);
+  if (e != hipSuccess) return e;
+  host_tick += kTicksPerGraph;
+  e = hipEventRecord(launch_ev[launch_pos], stream);
+  launch_used[launch_pos] = true;
+  launch_pos = (launch_pos + 1) % kInFlight;
+  return e;
+}
+
+// Destroys the replaced graphs whose launches have completed.
+void Engine::collect_graphs(bool all) {
+  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> keep;
+  for (auto& ge : old_graphs) {
+    const hipError_t q = all ? hipEventSynchronize(ge.second) : hipEventQuery(ge.second);
+    if (q == hipErrorNotReady) {
+      keep.push_back(ge);
+      continue;
+    }
+    (void)hipGraphExecDestroy(ge.first);
+    spare_events.push_back(ge.second);
+  }
+  old_graphs.swap(keep);
 }
 
 void Engine::retire(bool block) {
@@ -407,12 +645,24 @@ void Engine::run() {
       if (stop) break;
     }
     admit();
-    tick();
-    bool idle_launches = running.empty();
-    retire(idle_launches && !finishing.empty());
+    leave_finished();
+    if (!running.empty()) {
+      hipError_t e = upload_lists();
+      if (e == hipSuccess) e = launch_ticks();
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        poisoned = true;   // every running request fails at the next pass
+      }
+    } else if (!buckets.empty()) {
+      // no members left: the empty lists still go up before any later launch
+      (void)upload_lists();
+    }
+    retire(running.empty() && !finishing.empty());
+    collect_graphs(false);
   }
   (void)hipStreamSynchronize(stream);
   for (hipStream_t l : lanes) (void)hipStreamSynchronize(l);
+  collect_graphs(true);
   for (auto* v : {&running, &finishing})
     for (auto& rp : *v) release(*rp);
 }
@@ -426,11 +676,12 @@ struct agg_engine {
 };
 
 static void engine_free(Engine& g) {
-  for (int i = 0; i < Engine::kRing; ++i) {
-    if (g.h_desc[i]) (void)hipHostFree(g.h_desc[i]);
-    if (g.d_desc[i]) (void)hipFree(g.d_desc[i]);
-    if (g.ring_ev[i]) (void)hipEventDestroy(g.ring_ev[i]);
-  }
+  if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+  for (int i = 0; i < Engine::kInFlight; ++i)
+    if (g.launch_ev[i]) (void)hipEventDestroy(g.launch_ev[i]);
+  for (auto& kv : g.buckets)
+    if (kv.second->list_ev) (void)hipEventDestroy(kv.second->list_ev);
+  g.buckets.clear();
   for (hipEvent_t ev : g.spare_events) (void)hipEventDestroy(ev);
   g.spare_events.clear();
   if (g.dev_base) (void)hipFree(g.dev_base);
@@ -473,10 +724,12 @@ agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g.fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc((void**)&g.dev_base, (size_t)c.mem_budget);
   if (e == hipSuccess) e = hipHostMalloc((void**)&g.host_base, (size_t)host_bytes, hipHostMallocDefault);
-  for (int i = 0; i < Engine::kRing && e == hipSuccess; ++i) {
-    e = hipHostMalloc((void**)&g.h_desc[i], sizeof(SlotDesc) * c.max_slots, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc((void**)&g.d_desc[i], sizeof(SlotDesc) * c.max_slots);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ring_ev[i], hipEventDisableTiming);
+  for (int i = 0; i < Engine::kInFlight && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&g.launch_ev[i], hipEventDisableTiming);
+  if (e == hipSuccess) {   // the tick counter: the first 256 bytes of the region, zeroed by a kernel
+    g.d_tick = (int64_t*)g.dev_base;
+    e = launch_zero((double*)g.d_tick, 1, g.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
   }
   if (e != hipSuccess) {
     agg_status rc = (e == hipErrorOutOfMemory) ? set_error(AGG_ENOMEM, "engine memory could not be reserved")
@@ -487,6 +740,8 @@ agg_status agg_engine_create(const agg_engine_config* cfg, agg_engine** out) {
     return rc;
   }
   g.dev.init((size_t)c.mem_budget);
+  size_t tick_off = 0;
+  (void)g.dev.alloc(256, &tick_off);   // offset 0: the tick counter
   g.host.init((size_t)host_bytes);
   g.worker = std::thread([&g] { g.run(); });
   *out = E;
@@ -527,7 +782,11 @@ agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms
   std::vector<std::vector<double>>().swap(r->tab.ucols);   // now in the image
   if ((rc = row_lds_check(r->tab, r->im.ntab, r->im.Tp + r->im.Tq))) return rc;
   r->lay = request_layout(r->tab, r->im.bytes.size());
-  if ((int64_t)r->lay.dev_total > g.cfg.mem_budget || r->lay.host_total > g.host.size)
+  // with the block of its bucket (slot table, lists, twiddles) and the tick counter
+  const size_t bucket_dev = align256(sizeof(SlotDesc) * (size_t)g.cap_slots) +
+                            align256(sizeof(int) * (size_t)(g.cap_slots + 1)) + (r->lay.o_n - r->im.o_tw1);
+  if ((int64_t)(r->lay.dev_total + bucket_dev + 256) > g.cfg.mem_budget ||
+      r->lay.host_total + align256(sizeof(int) * (size_t)(g.cap_slots + 1)) > g.host.size)
     return set_error(AGG_ENOMEM, "request footprint exceeds the engine budget");
   const size_t nb = (size_t)N * 8;
   Request* rr = r.get();

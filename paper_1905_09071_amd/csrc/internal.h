@@ -75,6 +75,7 @@ hipError_t launch_moments(const double* n, int64_t total, int64_t N, double* par
 hipError_t launch_heun(int stage, double* n, const double* k1, const double* k2, double* ntil, double dt,
                        int64_t total, hipStream_t s);
 hipError_t launch_zero(double* x, int64_t total, hipStream_t s);
+hipError_t launch_tick(int64_t* t, hipStream_t s);
 size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max);
 size_t row_chunk_smem_bytes(int prec, int cmax, int umax, int M2, int tab_max, int coef_max);
 int col_batch(int prec, int M1, int u, int nworkgroups);

@@ -57,8 +57,17 @@ struct SlotDesc {
   int N, u, Tp, Tq;
   int mode;               // per-slot column mode (when the launch mode is < 0)
   int row_on;             // per-slot row pass switch (when the launch mode is < 0)
-  double dt;              // per-slot step (when the launch mode is < 0)
+  double dt;              // per-slot step (when the launch mode is < 0); the step
+                          //   of a solve's full steps (launches with a tick counter)
   double* out;            // per-slot RHS output (CM_RHS without external output)
+  // solves driven by a device tick counter (LaunchArgs::tick): the slot's stage
+  // is tick - start_tick (0: forward pass of n(0); 2s+1, 2s+2: the two Heun
+  // stages of step s < nsteps; anything else: nothing), the last step takes
+  // dt_last
+  int64_t start_tick;
+  int64_t nsteps;
+  double dt_last;
+  double pad_;            // (keeps the size a multiple of 16 bytes: whole 16-byte loads)
 };
 
 // Byte strides between consecutive slots' buffers when every slot of a launch
@@ -90,6 +99,11 @@ struct LaunchArgs {
   int coef_max;           // largest coefficient blob (Tp + Tq) among the slots
   int lean;               // column pass variant for launches that fill the GPU
   double tilt;            // binary32 spectra: inputs weighted by exp(tilt s), gain by exp(-tilt s) (0: off)
+  // serving launches (captured once, replayed every tick): logical slot s of
+  // the launch is table entry active[1 + s] while s < active[0] (its workgroups
+  // exit otherwise), and each slot's stage follows from *tick (mode < 0)
+  const int* active;
+  const int64_t* tick;
 };
 
 constexpr int kColBatch = 4;             // upper bound of LaunchArgs::ub

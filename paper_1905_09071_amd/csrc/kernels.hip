@@ -153,6 +153,38 @@ __device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
   return sd;
 }
 
+// Table entry of logical slot s of a launch (-1: beyond the launch's active list).
+__device__ __forceinline__ int launch_slot(const LaunchArgs& a, int s) {
+  if (!a.active) return s;
+  const auto act = uniform_ptr(a.active);
+  return s < act[0] ? act[1 + s] : -1;
+}
+
+// What a slot does in this launch: the column mode, whether the row pass runs,
+// and the step.  Launch-wide mode (>= 0), per-slot fields (< 0), or the stage
+// of a solve counted by the device tick counter.
+__device__ __forceinline__ void slot_stage(const LaunchArgs& a, const SlotDesc& sd, int& mode, int& row_on,
+                                           double& dt) {
+  if (a.mode >= 0) {
+    mode = a.mode; row_on = 1; dt = a.dt;
+  } else if (a.tick) {
+    const int64_t st = *uniform_ptr(a.tick) - sd.start_tick, ns = sd.nsteps;
+    if (st < 0 || st > 2 * ns) {
+      mode = CM_NONE; row_on = 0; dt = 0.0;
+    } else if (st == 0) {
+      mode = CM_FWD; row_on = 0; dt = 0.0;
+    } else {
+      const int64_t step = (st - 1) / 2;
+      const bool last = step == ns - 1;
+      row_on = 1;
+      dt = last ? sd.dt_last : sd.dt;
+      mode = (st & 1) ? CM_H1 : (last ? CM_H2 : CM_H2_FWD);
+    }
+  } else {
+    mode = sd.mode; row_on = sd.row_on; dt = sd.dt;
+  }
+}
+
 // Block index -> work index such that consecutive work indices run on the same
 // XCD (workgroups are dealt round-robin over the 8 XCDs), so neighbouring
 // column groups share one L2 and its cache lines are written whole.
@@ -218,12 +250,15 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   const int M2 = a.M2, g = a.g, lgg = a.lgg;
   const int ngroups = M2 >> lgg;
   const int w = xcd_contiguous(blockIdx.x, a.nslots * ngroups);
-  const int slot = w / ngroups;
-  const int grp = w - slot * ngroups;
+  const int lslot = w / ngroups;
+  const int grp = w - lslot * ngroups;
+  const int slot = launch_slot(a, lslot);
+  if (slot < 0) return;
   const SlotDesc sd = slot_desc(a, slot);
-  const int mode = a.mode >= 0 ? a.mode : sd.mode;
+  int mode, row_on_unused;
+  double dt;
+  slot_stage(a, sd, mode, row_on_unused, dt);
   if (mode == CM_NONE) return;
-  const double dt = a.mode >= 0 ? a.dt : sd.dt;
   const int64_t N = sd.N;
   const int64_t M = (int64_t)M1 * M2;
   const int j2_0 = grp * g;
@@ -529,10 +564,14 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
 
   const int M1 = a.M1;
   const int nwork = M1 / 2 + 1;
-  const int slot = blockIdx.x / nwork;
-  const int k1 = blockIdx.x - slot * nwork;
+  const int lslot = blockIdx.x / nwork;
+  const int k1 = blockIdx.x - lslot * nwork;
+  const int slot = launch_slot(a, lslot);
+  if (slot < 0) return;
   const SlotDesc sd = slot_desc(a, slot);
-  const int row_on = a.mode >= 0 ? 1 : sd.row_on;
+  int mode_unused, row_on;
+  double dt_unused;
+  slot_stage(a, sd, mode_unused, row_on, dt_unused);
   if (!row_on) return;
   const int u = sd.u;
   const int64_t M = (int64_t)M1 * M2;
@@ -863,10 +902,14 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
 
   const int M1 = a.M1;
   const int nwork = M1 / 2 + 1;
-  const int slot = blockIdx.x / nwork;
-  const int k1 = blockIdx.x - slot * nwork;
+  const int lslot = blockIdx.x / nwork;
+  const int k1 = blockIdx.x - lslot * nwork;
+  const int slot = launch_slot(a, lslot);
+  if (slot < 0) return;
   const SlotDesc sd = slot_desc(a, slot);
-  const int row_on = a.mode >= 0 ? 1 : sd.row_on;
+  int mode_unused, row_on;
+  double dt_unused;
+  slot_stage(a, sd, mode_unused, row_on, dt_unused);
   if (!row_on) return;
   const int u = sd.u;
   const int64_t M = (int64_t)M1 * M2;
@@ -1057,6 +1100,17 @@ hipError_t launch_heun(int stage, double* n, const double* k1, const double* k2,
   int64_t blocks = (total + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(heun_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, stage, n, k1, k2, ntil, dt, total);
+  return hipGetLastError();
+}
+
+// The serving engine's tick counter: one increment per tick, after every
+// launch of the tick (stream order).
+__global__ void tick_kernel(int64_t* t) {
+  if (threadIdx.x == 0) t[0] += 1;
+}
+
+hipError_t launch_tick(int64_t* t, hipStream_t s) {
+  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, s, t);
   return hipGetLastError();
 }
 
