@@ -103,6 +103,34 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
                            agg_plan** out);
 agg_status agg_plan_destroy(agg_plan* plan);
 
+/* One collision order d with its kernel in tensor-train form (Sec. 2, the TT
+ * decomposition of the kernel tensor):
+ *   C^(d)_{i_1..i_d} = sum_{r_1..r_{d-1}} H^(1)_{1,i_1,r_1} H^(2)_{r_1,i_2,r_2} ... H^(d)_{r_{d-1},i_d,1}.
+ * ranks: r_0..r_d (r_0 = r_d = 1, the others in [1, 8]); H[m-1] is a HOST
+ * pointer to core m as r_{m-1} x r_m columns of N doubles:
+ *   H[m-1][(a*r_m + b)*N + (i-1)] = H^(m)_{a, i, b}   (m = 1..d; mode d is the k-mode).
+ * Entries past d are ignored. */
+typedef struct {
+  int32_t d;
+  int32_t ranks[AGG_MAX_D + 1];
+  const double* H[AGG_MAX_D];
+} agg_tt_term;
+
+/* agg_plan_create for kernels in tensor-train form: the method of Sec. 1 at its
+ * O(N D R^2 log N) cost.  Every distinct non-zero core column is weighted by
+ * the state and transformed once; per frequency bin the gain of order d is the
+ * product of the d cores' r_{m-1} x r_m matrices of spectra (times 1/d!), and
+ * the loss weights of order d come from the product of the first d-1 cores'
+ * matrices of dot products U_c . n (times 1/(d-1)!), applied to core d's
+ * columns.  Same state layout, calls (agg_rhs, agg_rk2_step, agg_solve,
+ * agg_rhs_noalloc) and precisions as a CP plan; no AGG_PLAIN option.
+ * Errors: as agg_plan_create, and AGG_EINVAL for ranks outside [1, 8] or
+ * r_0, r_d != 1; AGG_EUNSUPPORTED when the transform's rows exceed 512 values
+ * (N D above 2^20) or one core has more distinct columns than a row-pass chunk
+ * holds. */
+agg_status agg_plan_create_tt(int32_t D, int64_t N, const agg_tt_term* terms, int32_t nterms,
+                              int32_t prec, int32_t batch, void* hip_stream, agg_plan** out);
+
 /* Exponential tilting of a binary32 plan's gain transforms (a numerical device,
  * not in the paper).  The gain term of Sec. 1 is a sum of d-fold convolutions,
  * and the convolution of inputs scaled by exp(theta s) is the convolution scaled
@@ -201,6 +229,14 @@ agg_status agg_profile_pass(agg_plan* plan, const double* n, int32_t pass, int32
 agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
                            int32_t prec, int64_t* out, int64_t cap, int64_t* len);
 agg_status agg_twiddles(int64_t P, double* out);
+/* agg_plan_tables for a tensor-train kernel set:
+ * [L, M1, M2, g, u, number of terms T, number of cores K, effective order,
+ *  per term: d,
+ *  per core (terms by ascending d, cores m = 1..d): term index, m, r_{m-1}, r_m,
+ *    column ids of its r_{m-1} x r_m columns (row-major, -1 for an all-zero column),
+ *  number of row-pass chunks H, per chunk: ncols, ncores, column ids, core indices] */
+agg_status agg_plan_tables_tt(int32_t D, int64_t N, const agg_tt_term* terms, int32_t nterms,
+                              int32_t prec, int64_t* out, int64_t cap, int64_t* len);
 
 /* ---- host kernel compression (no device is touched) ------------------------
  * For kernels that depend on the total size only, C^(d)_{i_1..i_d} =

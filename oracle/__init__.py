@@ -16,6 +16,10 @@ modelling multi-particle interactions"):
 * ``heun_solve``   explicit second-order Runge-Kutta (Heun) time stepping (Sec. 3)
 * closed forms     constant-kernel zeroth moment, binary constant kernel
 * ``plan_tables``  the written integer plan rules, implemented independently
+                   (``plan_tables_tt`` for kernels in tensor-train form)
+* ``tt_full``, ``tt_paths``, ``rhs_dense``  kernels in tensor-train form (Sec. 2):
+                   the dense tensor, its rank-path CP factors, and the literal
+                   sums from dense kernel tensors
 * ``twiddles_ref`` correctly rounded roots of unity via mpmath
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline leg
@@ -27,5 +31,6 @@ from .spectral import rhs_fft, total_rhs  # noqa: F401
 from .heun import heun_solve, time_grid  # noqa: F401
 from .closed_forms import (m0_constant_kernel_d3, m0_rhs_constant_kernel,  # noqa: F401
                            binary_constant_monodisperse, scalar_heun)
-from .plan import plan_tables  # noqa: F401
+from .plan import plan_tables, plan_tables_tt  # noqa: F401
+from .tt import tt_full, tt_paths, rhs_dense  # noqa: F401
 from .sum_kernel import rhs_sum_kernel  # noqa: F401

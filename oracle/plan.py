@@ -134,3 +134,85 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = 
         flat += [len(cols), len(terms)] + cols + terms
     return dict(L=L, M=M, M1=M1, M2=M2, g=g, u=u, De=De, colmap=colmap,
                 pterms=pterms, qterms=qterms, chunks=chunks, flat=np.array(flat, dtype=np.int64))
+
+
+def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64"):
+    """The written rules for kernels in tensor-train form (Sec. 2): {d: cores},
+    core m of shape (r_{m-1}, N, r_m).
+
+    T1  Effective order and L as P1/P2 (De = largest d listed).
+    T2  Column ids: scan d ascending, cores m = 1..d, a < r_{m-1}, b < r_m; the
+        core column H^(m)[a, :, b] gets -1 when all its values are zero, else the
+        id of the first earlier bitwise-equal column, else the next new id.
+    T3  Split and tile as P6/P7 with u distinct columns.  Unsupported when M2 > 512.
+    T4  Chunks always (the chain runs in the chunked row pass): capacity as in
+        P8, cores taken in scan order, a chunk taking the next core while the
+        union of distinct non-negative ids stays within the capacity, else a
+        new chunk starts with that core.  Unsupported if one core alone has
+        more distinct ids than the capacity.
+
+    Flat table: [L, M1, M2, g, u, T, K, De, d per term,
+                 per core: term, m, r_in, r_out, ids[r_in r_out] (row-major),
+                 nchunks, per chunk: ncols, ncores, ids, core indices]."""
+    orders = sorted(tt)
+    De = max(orders) if orders else 2
+    L = 1
+    while L < De * N - 1:
+        L *= 2
+    L = max(16, L)
+    M = L // 2
+    seen = []
+    cores_rec = []       # (term, m, rin, rout, ids)
+    for t, d in enumerate(orders):
+        for m in range(1, d + 1):
+            H = np.asarray(tt[d][m - 1], dtype=np.float64)
+            rin, rout = H.shape[0], H.shape[2]
+            ids = []
+            for a in range(rin):
+                for b in range(rout):
+                    col = np.ascontiguousarray(H[a, :, b])
+                    if not np.any(col != 0.0):
+                        ids.append(-1)
+                        continue
+                    key = col.tobytes()
+                    if key in seen:
+                        ids.append(seen.index(key))
+                    else:
+                        seen.append(key)
+                        ids.append(len(seen) - 1)
+            cores_rec.append((t, m, rin, rout, ids))
+    u = len(seen)
+    cs = PREC_BYTES[prec]
+    lg = _log2_exact(M)
+    M1 = 1 << ((lg + 1) // 2)
+    M2 = M // M1
+    while u * 2 * M2 * cs > 65536 and M1 < 2048:
+        M1 *= 2
+        M2 //= 2
+    if M1 > 2048 or M2 < 2:
+        raise Unsupported(f"no two-pass split for L={L} with u={u}")
+    if M2 > 512:
+        raise Unsupported("tensor-train chains need rows of at most 512 values")
+    g = min(M2, max(1, 1024 // M1))
+    cmax = 151552 // (2 * (M2 + M2 // 16) * cs)
+    chunks = []
+    cols, cores = set(), []
+    for k, rec in enumerate(cores_rec):
+        need = {i for i in rec[4] if i >= 0}
+        if len(need) > cmax:
+            raise Unsupported(f"a core has {len(need)} distinct columns; a chunk holds {cmax}")
+        if cores and len(cols | need) > cmax:
+            chunks.append((sorted(cols), cores))
+            cols, cores = set(), []
+        cols |= need
+        cores.append(k)
+    if cores:
+        chunks.append((sorted(cols), cores))
+    flat = [L, M1, M2, g, u, len(orders), len(cores_rec), De] + list(orders)
+    for (t, m, rin, rout, ids) in cores_rec:
+        flat += [t, m, rin, rout] + ids
+    flat.append(len(chunks))
+    for cols, cores in chunks:
+        flat += [len(cols), len(cores)] + cols + cores
+    return dict(L=L, M1=M1, M2=M2, g=g, u=u, De=De, cores=cores_rec, chunks=chunks,
+                flat=np.array(flat, dtype=np.int64))

@@ -13,9 +13,10 @@ import numpy as np
 
 from ._lib import (AGG_EINVAL, AGG_ENOMEM, AGG_ENONFINITE, AGG_ENOTFOUND, AGG_EUNSUPPORTED,  # noqa: F401
                    AGG_OK, AGG_PENDING, AGG_MAX_D, PREC, AggError, agg_engine_config,
-                   agg_request_stats, agg_solve_stats, agg_term, check, lib)
+                   agg_request_stats, agg_solve_stats, agg_term, agg_tt_term, check, lib)
 
-__all__ = ["Plan", "Engine", "plan_tables", "twiddles", "expsum_fit", "tt_expand", "AggError", "PREC", "make_terms"]
+__all__ = ["Plan", "Engine", "plan_tables", "plan_tables_tt", "twiddles", "expsum_fit", "tt_expand", "AggError",
+           "PREC", "make_terms", "make_tt_terms"]
 
 
 def make_terms(D: int, N: int, kernel: dict):
@@ -52,6 +53,43 @@ def make_terms(D: int, N: int, kernel: dict):
             keep.append(wv)
             arr[t].weight = wv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return arr, len(items), keep
+
+
+def make_tt_terms(D: int, N: int, tt: dict):
+    """Build the agg_tt_term array from {d: [core_1, ..., core_d]}, core m an
+    array of shape (r_{m-1}, N, r_m) with H[a, i-1, b] = H^(m)_{a, i, b};
+    returns (array, count, keepalive list)."""
+    items = sorted(tt.items())
+    arr = (agg_tt_term * max(len(items), 1))()
+    keep = []
+    for t, (d, cores) in enumerate(items):
+        if len(cores) != d:
+            raise ValueError(f"order {d} needs {d} cores")
+        ranks = [int(np.shape(cores[0])[0])] + [int(np.shape(c)[2]) for c in cores]
+        for m in range(d):
+            if np.ndim(cores[m]) != 3 or np.shape(cores[m])[1] != N or np.shape(cores[m])[0] != ranks[m]:
+                raise ValueError(f"order {d}, core {m + 1}: shape (r_{m}, N, r_{m + 1}) expected")
+        arr[t].d = d
+        for m, r in enumerate(ranks):
+            arr[t].ranks[m] = r
+        for m in range(d):
+            # (r_{m-1}, N, r_m) -> r_{m-1} x r_m columns of N values
+            col = np.ascontiguousarray(np.transpose(np.asarray(cores[m], dtype=np.float64), (0, 2, 1)))
+            keep.append(col)
+            arr[t].H[m] = col.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return arr, len(items), keep
+
+
+def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64") -> np.ndarray:
+    """The planner's integer tables of a tensor-train kernel set (host only)."""
+    terms, nt, keep = make_tt_terms(D, N, tt)
+    ln = ctypes.c_int64(0)
+    lib().agg_plan_tables_tt(D, N, terms, nt, PREC[prec], None, 0, ctypes.byref(ln))
+    out = np.zeros(max(ln.value, 1), dtype=np.int64)
+    check(lib().agg_plan_tables_tt(D, N, terms, nt, PREC[prec],
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.size, ctypes.byref(ln)))
+    del keep
+    return out[:ln.value]
 
 
 AGG_PLAIN = 0x100
@@ -128,16 +166,25 @@ def _check_state(t, numel):
 class Plan:
     """agg_plan: a kernel set, precision and batch size bound to a stream."""
 
-    def __init__(self, D: int, N: int, kernel: dict, prec: str = "fp64", batch: int = 1, stream=None,
-                 plain: bool = False):
-        """plain=True: the term-by-term, unshared, unfused reference evaluation."""
+    def __init__(self, D: int, N: int, kernel: dict = None, prec: str = "fp64", batch: int = 1, stream=None,
+                 plain: bool = False, tt: dict = None):
+        """plain=True: the term-by-term, unshared, unfused reference evaluation.
+        tt={d: cores}: the kernel set in tensor-train form instead of CP factors
+        (agg_plan_create_tt)."""
         self.D, self.N, self.batch, self.prec, self.plain = D, N, batch, prec, plain
-        terms, nt, keep = make_terms(D, N, kernel)
         self._stream = stream
         h = ctypes.c_void_p()
-        code = PREC[prec] | (AGG_PLAIN if plain else 0)
-        check(lib().agg_plan_create(D, N, terms, nt, code, batch, _stream_handle(stream),
-                                    ctypes.byref(h)))
+        if tt is not None:
+            if kernel is not None or plain:
+                raise ValueError("a tensor-train plan takes no CP kernel and no plain option")
+            terms, nt, keep = make_tt_terms(D, N, tt)
+            check(lib().agg_plan_create_tt(D, N, terms, nt, PREC[prec], batch, _stream_handle(stream),
+                                           ctypes.byref(h)))
+        else:
+            terms, nt, keep = make_terms(D, N, kernel)
+            code = PREC[prec] | (AGG_PLAIN if plain else 0)
+            check(lib().agg_plan_create(D, N, terms, nt, code, batch, _stream_handle(stream),
+                                        ctypes.byref(h)))
         del keep
         self._h = h
 

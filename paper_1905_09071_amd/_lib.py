@@ -24,6 +24,10 @@ class agg_term(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("rank", ctypes.c_int32), ("U", DP * AGG_MAX_D), ("weight", DP)]
 
 
+class agg_tt_term(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("ranks", ctypes.c_int32 * (AGG_MAX_D + 1)), ("H", DP * AGG_MAX_D)]
+
+
 class agg_solve_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("rhs_evals", ctypes.c_int64), ("t_final", ctypes.c_double),
                 ("m0_initial", ctypes.c_double), ("m1_initial", ctypes.c_double),
@@ -45,6 +49,12 @@ EXPORTS = [
     ("agg_plan_create", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_term), ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_void_p)]),
+    ("agg_plan_create_tt", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_tt_term),
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    ("agg_plan_tables_tt", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_tt_term),
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     ("agg_plan_destroy", ctypes.c_int32, [ctypes.c_void_p]),
     ("agg_plan_set_tilt", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double]),
     ("agg_rhs", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),

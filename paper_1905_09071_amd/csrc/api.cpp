@@ -137,7 +137,29 @@ SharedImage make_shared_image(const PlanTables& T) {
   // chunk with ids local to the chunk (position in its column list)
   std::vector<int> torder, tchunk;
   std::vector<std::vector<int>> tids;
-  if (T.cmax == 0) {
+  std::vector<int> tt_rec, tt_loc, tt_glob;   // tensor-train cores (see SlotDesc::o_tt)
+  if (T.tt) {
+    for (size_t c = 0; c < T.ch_cols.size(); ++c) {
+      const std::vector<int>& cc = T.ch_cols[c];
+      for (int id : cc) ch_cols.push_back(id);
+      ch_coff.push_back((int)ch_cols.size());
+      for (int k : T.ch_terms[c]) {
+        const int t = T.tc_term[k];
+        tt_rec.insert(tt_rec.end(), {t, T.tc_lambda[k], T.tt_d[t], T.tc_rin[k], T.tc_rout[k], (int)tt_loc.size(),
+                                     (int)tt_glob.size()});
+        for (int j = 0; j < T.tc_rin[k] * T.tc_rout[k]; ++j) {
+          const int id = T.tc_ids[T.tc_off[k] + j];
+          tt_glob.push_back(id);
+          tt_loc.push_back(id < 0 ? -1 : (int)(std::lower_bound(cc.begin(), cc.end(), id) - cc.begin()));
+        }
+      }
+      ch_toff.push_back((int)(tt_rec.size() / 7));
+    }
+    for (int d : T.tt_d) {
+      coef.push_back(1.0 / factorial(d));
+      coef.push_back(1.0 / factorial(d - 1));
+    }
+  } else if (T.cmax == 0) {
     for (size_t t = 0; t < T.p_ids.size(); ++t) { torder.push_back((int)t); tchunk.push_back(0); tids.push_back(T.p_ids[t]); }
   } else {
     for (size_t c = 0; c < T.ch_cols.size(); ++c) {
@@ -189,6 +211,15 @@ SharedImage make_shared_image(const PlanTables& T) {
   im.o_chc = put(ch_coff);
   im.o_chcols = put(ch_cols);
   im.o_cht = put(ch_toff);
+  if (T.tt) {
+    im.tt = (int)T.tt_d.size();
+    im.o_tt = put(tt_rec);
+    const int o_loc = put(tt_loc), o_glob = put(tt_glob);
+    for (size_t r = 0; r < tt_rec.size(); r += 7) {   // offsets relative to the blob
+      blob[im.o_tt + r + 5] += o_loc;
+      blob[im.o_tt + r + 6] += o_glob;
+    }
+  }
   im.ntab = (int)blob.size();
   im.Tp = (int)T.p_ids.size();
   im.Tq = (int)T.q_ids.size();
@@ -236,6 +267,7 @@ void bind_shared(const SharedImage& im, void* dev, SharedTables* st) {
   st->Tp = im.Tp; st->Tq = im.Tq; st->ntab = im.ntab;
   st->o_pids = im.o_pids; st->o_qoff = im.o_qoff; st->o_qids = im.o_qids; st->o_qkm = im.o_qkm; st->o_pfrom = im.o_pfrom;
   st->nch = im.nch; st->o_chc = im.o_chc; st->o_chcols = im.o_chcols; st->o_cht = im.o_cht;
+  st->tt = im.tt; st->o_tt = im.o_tt;
 }
 
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st) {
@@ -282,6 +314,7 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   sd->tab = st.tabs; sd->coef = st.coef; sd->ntab = st.ntab;
   sd->o_pids = st.o_pids; sd->o_qoff = st.o_qoff; sd->o_qids = st.o_qids; sd->o_qkm = st.o_qkm; sd->o_pfrom = st.o_pfrom;
   sd->nch = st.nch; sd->o_chc = st.o_chc; sd->o_chcols = st.o_chcols; sd->o_cht = st.o_cht;
+  sd->tt = st.tt; sd->o_tt = st.o_tt;
   sd->N = (int)T.N; sd->u = T.u; sd->Tp = st.Tp; sd->Tq = st.Tq;
   sd->mode = CM_NONE; sd->row_on = 0; sd->dt = 0.0;
   if (stride) *stride = s;
@@ -382,6 +415,8 @@ agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t 
   return AGG_OK;
 }
 
+static agg_status plan_create_from(agg_plan* p, int32_t batch, void* hip_stream, agg_plan** out);
+
 static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, int32_t nterms, int prec,
                                    int32_t batch, void* hip_stream, bool dedup, agg_plan** out) {
   *out = nullptr;
@@ -389,6 +424,13 @@ static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, 
   std::string err;
   agg_status rc = plan_build(D, N, terms, nterms, prec, &p->tab, &err, dedup);
   if (rc != AGG_OK) { delete p; return set_error(rc, err); }
+  return plan_create_from(p, batch, hip_stream, out);
+}
+
+// Device tables, slots and workspace of a plan whose tables are built.
+static agg_status plan_create_from(agg_plan* p, int32_t batch, void* hip_stream, agg_plan** out) {
+  agg_status rc;
+  const int64_t N = p->tab.N;
   if (N > (int64_t)1 << 30) { delete p; return set_error(AGG_EUNSUPPORTED, "N too large"); }
   p->batch = batch;
   p->stream = (hipStream_t)hip_stream;
@@ -409,6 +451,31 @@ fail:
 }
 
 agg_status agg_plan_destroy(agg_plan* p);
+
+agg_status agg_plan_create_tt(int32_t D, int64_t N, const agg_tt_term* terms, int32_t nterms, int32_t prec,
+                              int32_t batch, void* hip_stream, agg_plan** out) {
+  if (!out) return set_error(AGG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");
+  if ((prec & ~0xff) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
+  agg_plan* p = new agg_plan();
+  std::string err;
+  agg_status rc = plan_build_tt(D, N, terms, nterms, prec, &p->tab, &err);
+  if (rc != AGG_OK) { delete p; return set_error(rc, err); }
+  return plan_create_from(p, batch, hip_stream, out);
+}
+
+agg_status agg_plan_tables_tt(int32_t D, int64_t N, const agg_tt_term* terms, int32_t nterms, int32_t prec,
+                              int64_t* out, int64_t cap, int64_t* len) {
+  PlanTables T;
+  std::string err;
+  agg_status rc = plan_build_tt(D, N, terms, nterms, prec, &T, &err);
+  if (rc != AGG_OK) return set_error(rc, err);
+  if (len) *len = (int64_t)T.flat.size();
+  if (!out || cap < (int64_t)T.flat.size()) return set_error(AGG_EINVAL, "output capacity too small");
+  std::memcpy(out, T.flat.data(), T.flat.size() * sizeof(int64_t));
+  return AGG_OK;
+}
 
 agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
                            int32_t prec_opt, int32_t batch, void* hip_stream, agg_plan** out) {

@@ -274,6 +274,7 @@ bool Engine::setup_device(Request& r) {
   s.ntab = r.st.ntab;
   s.o_pids = r.st.o_pids; s.o_qoff = r.st.o_qoff; s.o_qids = r.st.o_qids; s.o_qkm = r.st.o_qkm; s.o_pfrom = r.st.o_pfrom;
   s.nch = r.st.nch; s.o_chc = r.st.o_chc; s.o_chcols = r.st.o_chcols; s.o_cht = r.st.o_cht;
+  s.tt = r.st.tt; s.o_tt = r.st.o_tt;
   s.N = (int)r.tab.N; s.u = r.tab.u; s.Tp = r.st.Tp; s.Tq = r.st.Tq;
   s.mode = CM_NONE;
   s.nsteps = r.nsteps;

@@ -31,6 +31,7 @@ struct SharedTables {
   const double* coef = nullptr;    // coefficient blob
   int Tp = 0, Tq = 0, ntab = 0, o_pids = 0, o_qoff = 0, o_qids = 0, o_qkm = 0, o_pfrom = 0;
   int nch = 0, o_chc = 0, o_chcols = 0, o_cht = 0;
+  int tt = 0, o_tt = 0;
   void *twP1 = nullptr, *twP2 = nullptr, *twLlo = nullptr, *twLhi = nullptr;
 };
 
@@ -40,6 +41,7 @@ struct SharedImage {
   size_t o_cols = 0, o_tabs = 0, o_coef = 0, o_tw1 = 0, o_tw2 = 0, o_twlo = 0, o_twhi = 0;
   int Tp = 0, Tq = 0, ntab = 0, o_pids = 0, o_qoff = 0, o_qids = 0, o_qkm = 0, o_pfrom = 0;
   int nch = 0, o_chc = 0, o_chcols = 0, o_cht = 0;
+  int tt = 0, o_tt = 0;
 };
 SharedImage make_shared_image(const PlanTables& T);
 void bind_shared(const SharedImage& im, void* dev, SharedTables* st);

@@ -67,7 +67,13 @@ struct SlotDesc {
   int64_t start_tick;
   int64_t nsteps;
   double dt_last;
-  double pad_;            // (keeps the size a multiple of 16 bytes: whole 16-byte loads)
+  // kernels in tensor-train form: number of chain terms (0: CP terms) and the
+  // offset of the core records in the int blob (7 ints per core: term, lambda,
+  // d, r_in, r_out, offset of its chunk-local ids, offset of its global ids;
+  // with nch chunks whose ch_toff ranges are core ranges); the coefficient blob
+  // holds 1/d! and 1/(d-1)! per chain term
+  int tt;
+  int o_tt;
 };
 
 // Byte strides between consecutive slots' buffers when every slot of a launch
@@ -114,5 +120,6 @@ constexpr int kLeanWorkgroups = 512;     // column-pass workgroups from which a 
 constexpr int kLeanMaxM1 = 512;          // largest column length with a lean column-pass variant
 constexpr int kRowRegCols = 4;          // row pass: distinct columns up to which unpacked spectra stay in registers
 constexpr int kSpreadWorkgroups = 256;   // column-pass workgroups a small launch is spread over (one per CU)
+constexpr int kTTMaxRank = 8;            // largest tensor-train rank (the chain's per-bin vectors live in registers)
 
 }  // namespace agg

@@ -962,6 +962,15 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
   cplx<T> YA[UPT], YB[UPT];
 #pragma unroll
   for (int i = 0; i < UPT; ++i) YA[i] = YB[i] = czero<T>();
+  // tensor-train kernels: the running row vector of a term's matrix chain at
+  // the unit's two bins, carried across chunks (cores); rows of at most 512
+  // values only (the planner's limit), so other lengths compile it out
+  constexpr bool TTK = M2 <= 512;
+  constexpr int TTU = TTK ? UPT : 1, TTR = TTK ? kTTMaxRank : 1;
+  cplx<T> vA[TTU][TTR], vB[TTU][TTR];
+  const bool tt = TTK && sd.tt > 0;
+  const auto ttrec = uniform_ptr(sd.tab + sd.o_tt);
+  const auto ttid = uniform_ptr(sd.tab);
   for (int h = 0; h < nch; ++h) {
     const int c0 = chunked ? chc[h] : 0;
     const int nc = chunked ? chc[h + 1] - c0 : uniform_int(u);
@@ -1008,6 +1017,55 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
         X[(c * nrows) * STR + lds_pad(iA)] = cnorm(xa);
         if (zero_bin) nyq[c] = cnorm(xb);
         else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
+      }
+      if constexpr (TTK) {
+        if (tt) {
+          // cores [t0, t1) of this chunk: v <- v * (the core's matrix of
+          // spectra at this bin); the first core of a term starts v, the last
+          // adds v[0] / d! to the gain
+          auto xat = [&](int c, bool b) -> cplx<T> {
+            if (c < 0) return czero<T>();
+            if (!b) return X[(c * nrows) * STR + lds_pad(iA)];
+            return zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)];
+          };
+          for (int k = t0; k < t1; ++k) {
+            const int term = ttrec[7 * k], lam = ttrec[7 * k + 1], d = ttrec[7 * k + 2];
+            const int rin = ttrec[7 * k + 3], rout = ttrec[7 * k + 4], lo = ttrec[7 * k + 5];
+            cplx<T> nA[TTR], nB[TTR];
+#pragma unroll
+            for (int b = 0; b < TTR; ++b) {
+              nA[b] = nB[b] = czero<T>();
+              if (b < rout) {
+                if (lam == 1) {
+                  nA[b] = xat(ttid[lo + b], false);
+                  nB[b] = xat(ttid[lo + b], true);
+                } else {
+#pragma unroll
+                  for (int a2 = 0; a2 < TTR; ++a2) {
+                    if (a2 < rin) {
+                      const int c = ttid[lo + a2 * rout + b];
+                      if (c >= 0) {
+                        nA[b] = cadd(nA[b], cmul(vA[i][a2], xat(c, false)));
+                        nB[b] = cadd(nB[b], cmul(vB[i][a2], xat(c, true)));
+                      }
+                    }
+                  }
+                }
+              }
+            }
+#pragma unroll
+            for (int b = 0; b < TTR; ++b) {
+              vA[i][b] = cnorm(nA[b]);
+              vB[i][b] = cnorm(nB[b]);
+            }
+            if (lam == d) {
+              const T cf = Real<T>::from_d(pcoef[2 * term]);
+              YA[i] = cnorm(cadd(YA[i], cscale(vA[i][0], cf)));
+              YB[i] = cnorm(cadd(YB[i], cscale(vB[i][0], cf)));
+            }
+          }
+          continue;
+        }
       }
       cplx<T> PA = czero<T>(), PB = czero<T>();
       for (int t = t0; t < t1; ++t) {
@@ -1067,6 +1125,45 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
       sdot[c] = t;
     }
     lds_barrier();
+    if (tt) {
+      // tensor-train terms: w = the product of the first d-1 cores' matrices
+      // of dot products (a row vector), then G_c += w_r / (d-1)! for core d's
+      // column c = (r, 0) (one thread: a few small products)
+      double* gacc = sdot + a.umax;
+      for (int c = tid; c < u; c += NT) gacc[c] = 0.0;
+      lds_barrier();
+      if (tid == 0) {
+        double w[kTTMaxRank];
+        const int ncores = ldg(sd.tab + sd.o_cht + sd.nch);
+        for (int k = 0; k < ncores; ++k) {
+          const int* cr = sd.tab + sd.o_tt + 7 * k;
+          const int term = ldg(cr), lam = ldg(cr + 1), d = ldg(cr + 2), rin = ldg(cr + 3), rout = ldg(cr + 4);
+          const int* gid = sd.tab + ldg(cr + 6);
+          if (lam == d) {
+            const double cq = ldg(sd.coef + 2 * term + 1);
+            for (int r = 0; r < rin; ++r) {
+              const int c = ldg(gid + r * rout);
+              if (c >= 0) gacc[c] += cq * w[r];
+            }
+            continue;
+          }
+          double nw[kTTMaxRank];
+          for (int b = 0; b < rout; ++b) {
+            double acc = 0.0;
+            for (int r = 0; r < rin; ++r) {
+              const int c = ldg(gid + r * rout + b);
+              const double s = c >= 0 ? sdot[c] : 0.0;
+              acc += (lam == 1 ? 1.0 : w[r]) * s;
+            }
+            nw[b] = acc;
+          }
+          for (int b = 0; b < rout; ++b) w[b] = nw[b];
+        }
+      }
+      lds_barrier();
+      for (int c = tid; c < u; c += NT) stg(sd.G + c, gacc[c]);
+      return;
+    }
     const int* qoff = sd.tab + sd.o_qoff;
     const int* qids = sd.tab + sd.o_qids;
     const int* qkm = sd.tab + sd.o_qkm;
@@ -1238,8 +1335,9 @@ size_t row_smem_bytes(int prec, int umax, int M2, int tab_max, int coef_max) {
 
 size_t row_chunk_smem_bytes(int prec, int cmax, int umax, int M2, int, int) {
   size_t cs = prec == 1 ? 8 : 16;
+  // rows, Nyquist values, per-wave partial dots, dot products, loss weights (tensor-train terms)
   return (size_t)(M2 <= 512 ? M2 : 0) * cs + (size_t)cmax * 2 * lds_len(M2) * cs + (size_t)cmax * cs +
-         (size_t)(2 * kThreads / 64 + 1) * umax * 8 + 16;
+         (size_t)(2 * kThreads / 64 + 2) * umax * 8 + 16;
 }
 
 int col_batch(int prec, int M1, int u, int nworkgroups) {

@@ -44,6 +44,24 @@ static int ilog2(int64_t x) {
   return l;
 }
 
+// Row-pass chunk capacity at a split: 148 KiB of rows at the padded LDS length.
+static int chunk_capacity(int M2, int cs) { return (int)(151552 / (2 * (M2 + M2 / 16) * cs)); }
+
+// The two-pass split (rules of plan_build).
+static agg_status split_pass(PlanTables& P, std::string* err) {
+  const int cs = complex_bytes(P.prec);
+  const int lg = ilog2(P.M);
+  int64_t M1 = int64_t(1) << ((lg + 1) / 2);
+  int64_t M2 = P.M / M1;
+  while ((int64_t)P.u * 2 * M2 * cs > 65536 && M1 < 2048) { M1 *= 2; M2 /= 2; }
+  if (M1 > 2048) { *err = "no two-pass split at this length"; return AGG_EUNSUPPORTED; }
+  if (M2 < 2) { *err = "too many distinct factor columns for the row pass at this length"; return AGG_EUNSUPPORTED; }
+  P.M1 = (int)M1; P.M2 = (int)M2;
+  P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1));
+  P.b = (ilog2(P.L) + 1) / 2;
+  return AGG_OK;
+}
+
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
                       PlanTables* out, std::string* err, bool dedup) {
   if (D < 2 || D > AGG_MAX_D) { *err = "D must lie in [2, AGG_MAX_D]"; return AGG_EINVAL; }
@@ -143,23 +161,17 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   }
 
   // two-pass split
-  int cs = complex_bytes(prec);
-  int lg = ilog2(P.M);
-  int64_t M1 = int64_t(1) << ((lg + 1) / 2);
-  int64_t M2 = P.M / M1;
-  while ((int64_t)P.u * 2 * M2 * cs > 65536 && M1 < 2048) { M1 *= 2; M2 /= 2; }
-  if (M1 > 2048) { *err = "no two-pass split at this length"; return AGG_EUNSUPPORTED; }
-  if (M2 < 2) { *err = "too many distinct factor columns for the row pass at this length"; return AGG_EUNSUPPORTED; }
-  P.M1 = (int)M1; P.M2 = (int)M2;
-  P.g = (int)std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1));
-  P.b = (ilog2(L) + 1) / 2;
+  const int cs = complex_bytes(prec);
+  agg_status src = split_pass(P, err);
+  if (src != AGG_OK) return src;
+  const int64_t M2 = P.M2;
 
   // chunks when the unchunked row pass's rows (at their padded LDS length) and
   // its twiddle table would not leave room for the term tables
   const int64_t row_need = (int64_t)P.u * 2 * (M2 + M2 / 16) * cs + (M2 <= 512 ? M2 * cs : 0);
   if (row_need > 147456) {
     // chunk capacity: 148 KiB of rows at the row pass's padded LDS length
-    P.cmax = (int)(151552 / (2 * (M2 + M2 / 16) * cs));
+    P.cmax = chunk_capacity((int)M2, cs);
     std::vector<std::pair<std::vector<int>, int>> order;   // (distinct ids, term)
     for (size_t t = 0; t < P.p_ids.size(); ++t) {
       std::vector<int> s = P.p_ids[t];                     // already ascending
@@ -186,7 +198,7 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
     if (!terms.empty()) { P.ch_cols.push_back(cols); P.ch_terms.push_back(terms); }
   }
 
-  P.flat = {L, M1, M2, P.g, P.u, (int64_t)P.p_ids.size(), (int64_t)P.q_ids.size(), De};
+  P.flat = {L, (int64_t)P.M1, M2, P.g, P.u, (int64_t)P.p_ids.size(), (int64_t)P.q_ids.size(), De};
   for (int id : P.colmap) P.flat.push_back(id);
   for (size_t t = 0; t < P.p_ids.size(); ++t) {
     P.flat.push_back((int64_t)P.p_ids[t].size());
@@ -205,6 +217,124 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
     P.flat.push_back((int64_t)P.ch_terms[c].size());
     for (int id : P.ch_cols[c]) P.flat.push_back(id);
     for (int t : P.ch_terms[c]) P.flat.push_back(t);
+  }
+  return AGG_OK;
+}
+
+agg_status plan_build_tt(int D, int64_t N, const agg_tt_term* terms, int nterms, int prec, PlanTables* out,
+                         std::string* err) {
+  if (D < 2 || D > AGG_MAX_D) { *err = "D must lie in [2, AGG_MAX_D]"; return AGG_EINVAL; }
+  if (N < 1) { *err = "N must be >= 1"; return AGG_EINVAL; }
+  if (prec != AGG_FP64 && prec != AGG_FP32 && prec != AGG_FP32C) { *err = "unknown precision"; return AGG_EINVAL; }
+  if (nterms < 0 || (nterms > 0 && terms == nullptr)) { *err = "bad term list"; return AGG_EINVAL; }
+  const agg_tt_term* byd[AGG_MAX_D + 1] = {nullptr};
+  for (int t = 0; t < nterms; ++t) {
+    const int d = terms[t].d;
+    if (d < 2 || d > D) { *err = "term order d outside [2, D]"; return AGG_EINVAL; }
+    if (byd[d]) { *err = "duplicate term order d"; return AGG_EINVAL; }
+    if (terms[t].ranks[0] != 1 || terms[t].ranks[d] != 1) { *err = "TT ranks r_0 and r_d must be 1"; return AGG_EINVAL; }
+    for (int m = 1; m < d; ++m)
+      if (terms[t].ranks[m] < 1 || terms[t].ranks[m] > kTTMaxRank) {
+        *err = "TT ranks must lie in [1, 8]"; return AGG_EINVAL;
+      }
+    for (int m = 0; m < d; ++m)
+      if (!terms[t].H[m]) { *err = "NULL TT core"; return AGG_EINVAL; }
+    byd[d] = &terms[t];
+  }
+  int De = 2;
+  for (int d = 2; d <= D; ++d) if (byd[d]) De = d;
+  if (N > (int64_t(1) << 40) || De * N - 1 > (int64_t(1) << 23)) {
+    *err = "transform length would exceed 2^23"; return AGG_EUNSUPPORTED;
+  }
+  for (int d = 2; d <= D; ++d) {
+    if (!byd[d]) continue;
+    for (int m = 0; m < d; ++m)
+      if (!all_finite(byd[d]->H[m], (int64_t)byd[d]->ranks[m] * byd[d]->ranks[m + 1] * N)) {
+        *err = "non-finite TT core"; return AGG_ENONFINITE;
+      }
+  }
+  PlanTables& P = *out;
+  P = PlanTables();
+  P.tt = true;
+  P.D = D; P.N = N; P.prec = prec; P.De = De;
+  int64_t L = 1;
+  while (L < De * N - 1) L *= 2;
+  P.L = std::max<int64_t>(L, 16); P.M = P.L / 2;
+
+  // columns: every core column, deduplicated bitwise; all-zero ones get -1
+  std::vector<const double*> uptr;
+  for (int d = 2; d <= D; ++d) {
+    if (!byd[d]) continue;
+    const int t = (int)P.tt_d.size();
+    P.tt_d.push_back(d);
+    for (int m = 1; m <= d; ++m) {
+      const int rin = byd[d]->ranks[m - 1], rout = byd[d]->ranks[m];
+      P.tc_term.push_back(t); P.tc_lambda.push_back(m);
+      P.tc_rin.push_back(rin); P.tc_rout.push_back(rout);
+      P.tc_off.push_back((int)P.tc_ids.size());
+      for (int a = 0; a < rin; ++a)
+        for (int b = 0; b < rout; ++b) {
+          const double* col = byd[d]->H[m - 1] + (size_t)(a * rout + b) * N;
+          bool zero = true;
+          for (int64_t i = 0; i < N && zero; ++i) zero = col[i] == 0.0;
+          int id = -1;
+          if (!zero) {
+            for (size_t j = 0; j < uptr.size(); ++j)
+              if (std::memcmp(uptr[j], col, sizeof(double) * (size_t)N) == 0) { id = (int)j; break; }
+            if (id < 0) { uptr.push_back(col); id = (int)uptr.size() - 1; }
+          }
+          P.tc_ids.push_back(id);
+        }
+    }
+  }
+  P.u = (int)uptr.size();
+  P.ucols.resize(P.u);
+  for (int c = 0; c < P.u; ++c) P.ucols[c].assign(uptr[c], uptr[c] + N);
+
+  agg_status rc = split_pass(P, err);
+  if (rc != AGG_OK) return rc;
+  if (P.M2 > 512) { *err = "tensor-train chains need rows of at most 512 values (N D <= 2^20)"; return AGG_EUNSUPPORTED; }
+
+  // chunks: whole cores in scan order
+  P.cmax = chunk_capacity(P.M2, complex_bytes(prec));
+  std::vector<int> cols, cores;
+  const int ncores = (int)P.tc_term.size();
+  for (int k = 0; k < ncores; ++k) {
+    std::vector<int> s;
+    for (int j = 0; j < P.tc_rin[k] * P.tc_rout[k]; ++j)
+      if (P.tc_ids[P.tc_off[k] + j] >= 0) s.push_back(P.tc_ids[P.tc_off[k] + j]);
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    if ((int)s.size() > P.cmax) { *err = "a TT core has more distinct columns than the row pass holds at this length"; return AGG_EUNSUPPORTED; }
+    std::vector<int> un;
+    std::set_union(cols.begin(), cols.end(), s.begin(), s.end(), std::back_inserter(un));
+    if (!cores.empty() && (int)un.size() > P.cmax) {
+      P.ch_cols.push_back(cols); P.ch_terms.push_back(cores);
+      cores.clear();
+      un = s;
+    }
+    cols = un;
+    cores.push_back(k);
+  }
+  if (!cores.empty()) { P.ch_cols.push_back(cols); P.ch_terms.push_back(cores); }
+  // the row pass sizes its LDS for the widest chunk
+  int widest = 1;
+  for (const auto& c : P.ch_cols) widest = std::max(widest, (int)c.size());
+  P.cmax = widest;
+
+  P.flat = {P.L, P.M1, P.M2, P.g, P.u, (int64_t)P.tt_d.size(), (int64_t)ncores, De};
+  for (int d : P.tt_d) P.flat.push_back(d);
+  for (int k = 0; k < ncores; ++k) {
+    P.flat.push_back(P.tc_term[k]); P.flat.push_back(P.tc_lambda[k]);
+    P.flat.push_back(P.tc_rin[k]); P.flat.push_back(P.tc_rout[k]);
+    for (int j = 0; j < P.tc_rin[k] * P.tc_rout[k]; ++j) P.flat.push_back(P.tc_ids[P.tc_off[k] + j]);
+  }
+  P.flat.push_back((int64_t)P.ch_cols.size());
+  for (size_t c = 0; c < P.ch_cols.size(); ++c) {
+    P.flat.push_back((int64_t)P.ch_cols[c].size());
+    P.flat.push_back((int64_t)P.ch_terms[c].size());
+    for (int id : P.ch_cols[c]) P.flat.push_back(id);
+    for (int k : P.ch_terms[c]) P.flat.push_back(k);
   }
   return AGG_OK;
 }

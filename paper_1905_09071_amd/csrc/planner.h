@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/agg.h"
+#include "kernels.h"
 
 namespace agg {
 
@@ -33,6 +34,16 @@ struct PlanTables {
   // each chunk's distinct column ids (ascending) and gain-term indices
   int cmax = 0;
   std::vector<std::vector<int>> ch_cols, ch_terms;
+  // kernels in tensor-train form (plan_build_tt; Sec. 2): order d's gain and
+  // loss sums are products of the d cores' matrices per frequency bin and of
+  // their dot-product matrices.  Cores are numbered in the order (term by
+  // ascending d, lambda = 1..d); core k belongs to term tc_term[k] as core
+  // tc_lambda[k], has tc_rin[k] x tc_rout[k] columns whose ids (row-major, -1
+  // for an all-zero column) start at tc_ids[tc_off[k]].  TT plans always run
+  // the chunked row pass: ch_cols as above, ch_terms holding core indices.
+  bool tt = false;
+  std::vector<int> tt_d;
+  std::vector<int> tc_term, tc_lambda, tc_rin, tc_rout, tc_off, tc_ids;
   std::vector<int64_t> flat;
 };
 
@@ -42,6 +53,18 @@ struct PlanTables {
 // evaluation); the rules are otherwise unchanged.
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
                       PlanTables* out, std::string* err, bool dedup = true);
+
+// The same for kernels given in tensor-train form: one agg_tt_term per order.
+// Adds to the rules of plan_build: column ids by first appearance scanning
+// terms by ascending d, cores lambda = 1..d, then a < r_{lambda-1}, b <
+// r_lambda (the core column H^(lambda)_{a,:,b}), all-zero columns getting -1;
+// row-pass chunks group whole cores in scan order, a chunk taking the next
+// core while the union of distinct ids stays within the chunk capacity.
+// Unsupported: ranks above kTTMaxRank, rows longer than 512 values (the
+// chain's per-bin vectors are held in registers), a core with more distinct
+// columns than a chunk holds.
+agg_status plan_build_tt(int D, int64_t N, const agg_tt_term* terms, int nterms, int prec, PlanTables* out,
+                         std::string* err);
 
 // exp(-2 pi i e / P) for e = 0..P-1, interleaved (re, im), binary64; and one entry.
 void twiddle_table(int64_t P, double* out);

@@ -81,3 +81,120 @@ def test_tt_pure_ternary_table1_shape(prec):
     say(f"  heun err {e:.3e}")
     assert e <= TOL[prec]
     plan.close()
+
+
+# ---- the tensor-train chain (agg_plan_create_tt): one transform per core
+# column, a product of the cores' matrices of spectra per frequency bin -------
+
+def _cores(rng, N, ranks):
+    return [rng.uniform(0.1, 1.0, size=(ranks[m], N, ranks[m + 1])) for m in range(len(ranks) - 1)]
+
+
+def _tt_rhs(D, N, tt, n, prec, batch=1, step=None):
+    plan = agg.Plan(D, N, prec=prec, tt=tt, batch=batch)
+    nt = torch.tensor(np.tile(n, batch), device=DEV)
+    f = plan.rhs(nt)
+    out = [f.cpu().numpy().reshape(batch, N)]
+    if step is not None:
+        plan.rk2_step(nt, step)
+        out.append(nt.cpu().numpy().reshape(batch, N))
+    torch.cuda.synchronize()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("N", [9, 13])
+def test_tt_chain_tiny_vs_literal_sums(prec, N):
+    """Random dense cores of orders 2..4 (ranks (1,2,1), (1,3,2,1), (1,2,3,2,1)),
+    one core column all zero and one shared between orders, against the
+    literal sums over the kernel tensors rebuilt from the cores."""
+    rng = np.random.default_rng(70 + N)
+    D = 4
+    tt = {2: _cores(rng, N, [1, 2, 1]), 3: _cores(rng, N, [1, 3, 2, 1]), 4: _cores(rng, N, [1, 2, 3, 2, 1])}
+    tt[3][1][2, :, 0] = 0.0
+    tt[4][3][1, :, 0] = tt[2][1][0, :, 0]
+    n = rng.uniform(0.0, 1.0, size=N)
+    f, = _tt_rhs(D, N, tt, n, prec)
+    ref = oracle.total_rhs(*[np.atleast_2d(x) for x in oracle.rhs_dense(D, N, {d: oracle.tt_full(c) for d, c in tt.items()}, n)])
+    e = rel(f[0], ref)
+    say(f"[tt chain tiny] N={N} {prec}: rhs err {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_tt_chain_random_dense_ranks_6(prec):
+    """D = 4, random dense cores with ranks (1,3,1), (1,4,4,1), (1,6,6,6,1) at
+    N = 4096 (84 + 16 + 3 distinct core columns), dense state, two states in a
+    batch: RHS and one Heun step against the oracle's CP-FFT evaluation of the
+    kernel written as its rank paths (216 + 16 + 3 rank-one terms)."""
+    rng = np.random.default_rng(80)
+    D, N = 4, 4096
+    tt = {2: _cores(rng, N, [1, 3, 1]), 3: _cores(rng, N, [1, 4, 4, 1]), 4: _cores(rng, N, [1, 6, 6, 6, 1])}
+    cp = {d: oracle.tt_paths(c) for d, c in tt.items()}
+    n = synth.n0_random_dense(N, 81, decay=2e-3)
+    h = 1e-5
+    f, after = _tt_rhs(D, N, tt, n, prec, batch=2, step=h)
+    rhs = lambda v: oracle.total_rhs(*oracle.rhs_fft(D, N, cp, v))
+    e = rel(f[1], rhs(n))
+    say(f"[tt chain ranks 6] {prec}: rhs err {e:.3e}")
+    assert e <= TOL[prec]
+    assert np.array_equal(f[0], f[1])
+    e = rel(after[0], oracle.heun_solve(rhs, n, h, h))
+    say(f"  heun err {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_tt_chain_brownian_equals_the_path_expansion(prec):
+    """The generalized Brownian cores of Sec. 2 (zero columns and ranks C(D, m))
+    through the chain agree with the same cores through the rank-path
+    expansion (both library paths), and with the oracle, at N = 65536."""
+    D, N = 4, 65536
+    mus = [0.3, -0.3, 0.1, 0.0]
+    tt = {d: synth.brownian_tt_cores(N, mus[:d]) for d in range(2, D + 1)}
+    n = synth.n0_random_dense(N, 62, decay=1e-4)
+    f, = _tt_rhs(D, N, tt, n, prec)
+    plan = agg.Plan(D, N, {d: agg.tt_expand(N, c) for d, c in tt.items()}, prec)
+    g = plan.rhs(torch.tensor(n, device=DEV)).cpu().numpy()
+    plan.close()
+    ref = oracle.total_rhs(*oracle.rhs_fft(D, N, {d: synth.kernel_generalized_brownian(N, mus[:d])
+                                                  for d in range(2, D + 1)}, n))
+    e1, e2 = rel(f[0], ref), rel(f[0], g)
+    say(f"[tt chain brownian] {prec}: vs oracle {e1:.3e}, vs path expansion {e2:.3e}")
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+
+
+_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_tt_chain_across_chunks(prec):
+    """The ranks-6 kernel set at N = 65536: the row pass holds 69 columns at a
+    time, so the 114 core columns come in three chunks and the order-4 chain
+    carries its per-bin vector across them.  Against the oracle's CP-FFT
+    evaluation of the rank paths (computed once for both precisions)."""
+    rng = np.random.default_rng(82)
+    D, N = 4, 65536
+    tt = {2: _cores(rng, N, [1, 3, 1]), 3: _cores(rng, N, [1, 4, 4, 1]), 4: _cores(rng, N, [1, 6, 6, 6, 1])}
+    ref_tables = oracle.plan_tables_tt(D, N, tt, prec)
+    assert len(ref_tables["chunks"]) == 3 and ref_tables["M2"] == 64
+    n = synth.n0_random_dense(N, 83, decay=1e-4)
+    f, = _tt_rhs(D, N, tt, n, prec)
+    if "ref" not in _REF:
+        cp = {d: oracle.tt_paths(c) for d, c in tt.items()}
+        _REF["ref"] = oracle.total_rhs(*oracle.rhs_fft(D, N, cp, n))
+    e = rel(f[0], _REF["ref"])
+    say(f"[tt chain chunks] {prec}: rhs err {e:.3e}")
+    assert e <= TOL[prec]
+
+
+def test_tt_chain_refusals():
+    rng = np.random.default_rng(5)
+    N = 64
+    with pytest.raises(agg.AggError) as e:   # rank above 8
+        agg.Plan(3, N, prec="fp64", tt={3: _cores(rng, N, [1, 9, 2, 1])})
+    assert e.value.status == agg.AGG_EINVAL
+    with pytest.raises(agg.AggError) as e:   # rows longer than 512 values
+        agg.Plan(2, 1 << 22, prec="fp64", tt={2: [np.ones((1, 1 << 22, 1)), np.ones((1, 1 << 22, 1))]})
+    assert e.value.status == agg.AGG_EUNSUPPORTED

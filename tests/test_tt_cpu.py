@@ -97,3 +97,95 @@ def test_tt_expand_refuses_a_path_explosion():
     with pytest.raises(agg.AggError) as e:
         agg.tt_expand(N, cores)
     assert e.value.status == agg.AGG_EUNSUPPORTED
+
+
+# ---- oracle pins for kernels in tensor-train form --------------------------
+
+def _random_cores(rng, N, ranks, positive=False):
+    lo = 0.1 if positive else -1.0
+    return [rng.uniform(lo, 1.0, size=(ranks[m], N, ranks[m + 1])) for m in range(len(ranks) - 1)]
+
+
+def test_oracle_tt_full_of_diagonal_cores_is_the_cp_tensor():
+    """A CP kernel of rank R is a TT kernel with ranks R whose inner cores are
+    diagonal: the oracle's contraction must give the CP tensor built here
+    directly from its definition."""
+    import oracle
+    rng = np.random.default_rng(21)
+    N, R, d = 5, 3, 3
+    U = rng.uniform(-1, 1, size=(d, R, N))
+    cores = [np.zeros((1, N, R)), np.zeros((R, N, R)), np.zeros((R, N, 1))]
+    for r in range(R):
+        cores[0][0, :, r] = U[0, r]
+        cores[1][r, :, r] = U[1, r]
+        cores[2][r, :, 0] = U[2, r]
+    assert np.abs(oracle.tt_full(cores) - dense_from_cp(U, N)).max() <= 1e-15
+
+
+def test_oracle_tt_paths_reproduce_the_contraction():
+    import oracle
+    rng = np.random.default_rng(22)
+    N = 5
+    cores = _random_cores(rng, N, [1, 2, 3, 1])
+    U = oracle.tt_paths(cores)
+    assert U.shape == (3, 6, N)
+    assert np.abs(dense_from_cp(U, N) - oracle.tt_full(cores)).max() <= 1e-14
+
+
+def test_oracle_rhs_dense_equals_the_literal_cp_sums():
+    """rhs_dense on the dense tensors of a CP kernel set equals rhs_direct (the
+    literal sums over the CP form, in C)."""
+    import oracle
+    rng = np.random.default_rng(23)
+    D, N = 4, 7
+    kernel = {2: rng.uniform(0, 1, size=(2, 2, N)), 3: rng.uniform(0, 1, size=(3, 3, N)),
+              4: rng.uniform(0, 1, size=(4, 2, N))}
+    n = rng.uniform(0, 1, size=N)
+    p, q = oracle.rhs_dense(D, N, {d: dense_from_cp(U, N) for d, U in kernel.items()}, n)
+    pr, qr = oracle.rhs_direct(D, N, kernel, n)
+    pr, qr = pr.sum(axis=0), qr.sum(axis=0)
+    assert np.abs(p - pr).max() <= 1e-14 * np.abs(pr).max()
+    assert np.abs(q - qr).max() <= 1e-14 * np.abs(qr).max()
+
+
+# ---- integer tables of tensor-train plans ----------------------------------
+
+def test_tt_tables_hand_derived():
+    """D=2, N=3, one order-2 term with ranks (1, 2, 1); core 2's second column
+    equals core 1's first.  L = 16 (max(16, 2^ceil(log2 5))), M = 8 -> M1 = 4,
+    M2 = 2, g = 2; ids: core 1 [0, 1], core 2 [2, 0]; u = 3; one chunk of
+    columns [0, 1, 2] holding cores [0, 1]."""
+    c1 = np.array([1.0, 2.0, 3.0])
+    c2 = np.array([0.5, 0.25, 0.125])
+    c3 = np.array([4.0, 5.0, 6.0])
+    core1 = np.zeros((1, 3, 2)); core1[0, :, 0] = c1; core1[0, :, 1] = c2
+    core2 = np.zeros((2, 3, 1)); core2[0, :, 0] = c3; core2[1, :, 0] = c1
+    want = [16, 4, 2, 2, 3, 1, 2, 2, 2,
+            0, 1, 1, 2, 0, 1,
+            0, 2, 2, 1, 2, 0,
+            1, 3, 2, 0, 1, 2, 0, 1]
+    got = agg.plan_tables_tt(2, 3, {2: [core1, core2]})
+    assert got.tolist() == want
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_tt_tables_match_the_twin(case):
+    import oracle
+    rng = np.random.default_rng(100 + case)
+    D = [2, 3, 4, 4, 3, 4][case]
+    N = [9, 40, 33, 257, 4096, 65536][case]
+    prec = ["fp64", "fp32", "fp32c", "fp64", "fp32c", "fp64"][case]
+    tt = {}
+    for d in range(2, D + 1):
+        ranks = [1] + [int(rng.integers(1, 7 if case < 5 else 7)) for _ in range(d - 1)] + [1]
+        cores = _random_cores(rng, N, ranks)
+        if d == 3 and ranks[1] > 1:
+            cores[1][1, :, 0] = 0.0                       # an all-zero column
+        if d == D and ranks[1] > 1:
+            cores[0][0, :, 1] = cores[0][0, :, 0]          # a duplicate within a core
+        if d > 2 and 2 in tt:
+            cores[-1][0, :, 0] = tt[2][1][0, :, 0]        # shared with another order
+        tt[d] = cores
+    got = agg.plan_tables_tt(D, N, tt, prec)
+    want = oracle.plan_tables_tt(D, N, tt, prec)["flat"]
+    assert got.tolist() == want.tolist()
