@@ -290,6 +290,35 @@ agg_status agg_expsum_fit(const double* f, int64_t smin, int64_t smax, int32_t R
 agg_status agg_tt_expand(int32_t d, int64_t N, const int32_t* ranks, const double* const* H, int64_t cap,
                          double* U, int64_t* npaths);
 
+/* Host: a kernel tensor of order d given by a function of the index tuple,
+ * approximated in tensor-train form by cross approximation (TT-cross: the
+ * method the paper builds its TT kernels with, Sec. 1, references on TT and
+ * TT-cross) - for kernels with no known CP or TT construction (general
+ * non-separable kernels, e.g. the ballistic kernel of binary aggregation).
+ *   f       callback: for count index tuples idx[t*d + m] (sizes, 1-based, mode
+ *           m+1) writes C at each into out[t]; called with up to 2^20 tuples
+ *           at a time; must be deterministic
+ *   tol     stop when the estimated error (below) is at most tol
+ *   rmax    largest TT rank, 1..8 (the ranks agg_plan_create_tt accepts)
+ *   max_sweeps  pairs of sweeps, >= 1; the ranks grow by one per pair while
+ *           the estimate exceeds tol
+ *   seed    of the random initial index sets and of the error sample
+ *   ranks   out, d+1 ranks (r_0 = r_d = 1)
+ *   cores   out, the cores in the agg_tt_term layout, core m (r_{m-1} x r_m
+ *           columns of N) starting after cores 1..m-1; capacity cap doubles
+ *   len     out, doubles written (or needed)
+ *   err_est out, max over 4096 random index tuples of |C_tt - C| / max |C|
+ * The train interpolates C exactly at the cross points (the index sets), and is
+ * then rounded (truncated SVDs along the train), so that the ranks returned are
+ * those the kernel numerically has up to rmax.
+ * Errors: AGG_EINVAL (bad sizes or pointers, rmax outside [1, 8], cap short:
+ * len, ranks and err_est are set), AGG_ENONFINITE (a non-finite value of f),
+ * AGG_EUNSUPPORTED (a singular cross), AGG_ENOMEM. */
+typedef void (*agg_kernel_fn)(const int64_t* idx, int64_t count, int32_t d, double* out, void* ctx);
+agg_status agg_tt_cross(int32_t d, int64_t N, agg_kernel_fn f, void* ctx, double tol, int32_t rmax,
+                        int32_t max_sweeps, uint64_t seed, int32_t* ranks, double* cores, int64_t cap,
+                        int64_t* len, double* err_est);
+
 /* ---- serving: continuous batching of whole solves ------------------------- */
 typedef struct {
   int32_t device;          /* HIP device ordinal                                 */

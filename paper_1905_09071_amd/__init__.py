@@ -13,10 +13,10 @@ import numpy as np
 
 from ._lib import (AGG_EINVAL, AGG_ENOMEM, AGG_ENONFINITE, AGG_ENOTFOUND, AGG_EUNSUPPORTED,  # noqa: F401
                    AGG_OK, AGG_PENDING, AGG_MAX_D, PREC, AggError, agg_engine_config,
-                   agg_request_stats, agg_solve_stats, agg_term, agg_tt_term, check, lib)
+                   agg_request_stats, agg_solve_stats, agg_term, agg_tt_term, check, lib, KERNEL_FN)
 
 __all__ = ["Plan", "Engine", "plan_tables", "plan_tables_tt", "twiddles", "expsum_fit", "tt_expand", "AggError",
-           "PREC", "make_terms", "make_tt_terms"]
+           "PREC", "make_terms", "make_tt_terms", "tt_cross"]
 
 
 def make_terms(D: int, N: int, kernel: dict):
@@ -139,6 +139,34 @@ def tt_expand(N: int, cores) -> np.ndarray:
     check(lib().agg_tt_expand(d, N, r, ptrs, npaths.value, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               ctypes.byref(npaths)))
     return U[:, :npaths.value]
+
+
+def tt_cross(d: int, N: int, f, tol: float = 1e-8, rmax: int = 8, max_sweeps: int = 12, seed: int = 0):
+    """TT-cross approximation (host) of the order-d kernel C(i_1..i_d) = f(idx),
+    f taking an int64 array of shape (count, d) of sizes (1-based) and
+    returning count values.  Returns (cores, err_est): cores[m] of shape
+    (r_m, N, r_{m+1}) as agg_plan_create_tt takes them."""
+    def cb(idx, count, dd, out, ctx):
+        a = np.ctypeslib.as_array(idx, shape=(count * dd,)).reshape(count, dd)
+        o = np.ctypeslib.as_array(out, shape=(count,))
+        o[:] = np.asarray(f(a), dtype=np.float64)
+    fn = KERNEL_FN(cb)
+    ranks = (ctypes.c_int32 * (d + 1))()
+    cap = d * rmax * rmax * N
+    buf = np.zeros(cap)
+    ln = ctypes.c_int64(0)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().agg_tt_cross(d, N, ctypes.cast(fn, ctypes.c_void_p), None, float(tol), int(rmax), int(max_sweeps),
+                             int(seed), ranks, buf.ctypes.data_as(dp), cap, ctypes.byref(ln), ctypes.byref(err)))
+    r = list(ranks)
+    cores, off = [], 0
+    for m in range(d):
+        size = r[m] * r[m + 1] * N
+        # stored as r_{m-1} x r_m columns of N: (a, b, i) -> (a, i, b)
+        cores.append(np.ascontiguousarray(buf[off:off + size].reshape(r[m], r[m + 1], N).transpose(0, 2, 1)))
+        off += size
+    return cores, err.value
 
 
 def twiddles(P: int) -> np.ndarray:

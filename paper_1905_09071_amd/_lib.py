@@ -24,6 +24,10 @@ class agg_term(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("rank", ctypes.c_int32), ("U", DP * AGG_MAX_D), ("weight", DP)]
 
 
+KERNEL_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
 class agg_tt_term(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("ranks", ctypes.c_int32 * (AGG_MAX_D + 1)), ("H", DP * AGG_MAX_D)]
 
@@ -72,6 +76,10 @@ EXPORTS = [
                                         DP, DP, DP]),
     ("agg_tt_expand", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(DP), ctypes.c_int64, DP, ctypes.POINTER(ctypes.c_int64)]),
+    ("agg_tt_cross", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_int32), DP, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64), DP]),
     ("agg_engine_create", ctypes.c_int32, [ctypes.POINTER(agg_engine_config), ctypes.POINTER(ctypes.c_void_p)]),
     ("agg_engine_destroy", ctypes.c_int32, [ctypes.c_void_p]),
     ("agg_submit", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_term),

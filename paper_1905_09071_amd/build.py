@@ -33,6 +33,7 @@ SOURCES = [
     ("planner.cpp", False),
     ("engine.cpp", False),
     ("compress.cpp", False),
+    ("cross.cpp", False),
 ]
 
 

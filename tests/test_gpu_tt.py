@@ -198,3 +198,35 @@ def test_tt_chain_refusals():
     with pytest.raises(agg.AggError) as e:   # rows longer than 512 values
         agg.Plan(2, 1 << 22, prec="fp64", tt={2: [np.ones((1, 1 << 22, 1)), np.ones((1, 1 << 22, 1))]})
     assert e.value.status == agg.AGG_EUNSUPPORTED
+
+
+def _ballistic(a):
+    s = a.astype(np.float64)
+    return np.sum(s ** (1 / 3), axis=1) ** 2 * np.sqrt(np.sum(1.0 / s, axis=1))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_tt_cross_kernel_through_the_chain(prec):
+    """A non-separable kernel with no CP or TT construction (the ballistic
+    kernel, cube roots squared times the root of the summed inverse sizes, at
+    orders 2 and 3) compressed by agg_tt_cross to ranks <= 8, then evaluated
+    through the chain: parity with the oracle's evaluation of the same cores
+    at N = 4096, and at N = 20 agreement with the literal sums over the exact
+    kernel to the compression's error."""
+    D = 3
+    for N in (20, 4096):
+        tt = {d: agg.tt_cross(d, N, _ballistic, tol=1e-12, rmax=8, seed=d)[0] for d in (2, 3)}
+        n = synth.n0_random_dense(N, 90, decay=1e-3 if N > 100 else 0.1)
+        f, = _tt_rhs(D, N, tt, n, prec)
+        if N == 4096:
+            ref = oracle.total_rhs(*oracle.rhs_fft(D, N, {d: oracle.tt_paths(c) for d, c in tt.items()}, n))
+            e = rel(f[0], ref)
+            say(f"[tt cross chain] N={N} {prec}: rhs err vs the cores' oracle evaluation {e:.3e}")
+            assert e <= TOL[prec]
+        else:
+            grid = lambda d: np.array(list(__import__("itertools").product(range(1, N + 1), repeat=d)))
+            exact = {d: _ballistic(grid(d)).reshape((N,) * d) for d in (2, 3)}
+            ref = oracle.total_rhs(*[np.atleast_2d(x) for x in oracle.rhs_dense(D, N, exact, n)])
+            e = rel(f[0], ref)
+            say(f"[tt cross chain] N={N} {prec}: rhs err vs the exact kernel {e:.3e}")
+            assert e <= 1e-5
