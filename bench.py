@@ -246,7 +246,9 @@ def oracle_reference(chk: dict):
     chk["t_end"] with step chk["dt"]."""
     import numpy as np
     import oracle
-    D, N, k = chk["D"], chk["N"], dense_factors(chk["kernel"])
+    D, N = chk["D"], chk["N"]
+    # a tensor-train kernel set enters as its rank-path CP factors
+    k = ({d: oracle.tt_paths(c) for d, c in chk["tt"].items()} if "tt" in chk else dense_factors(chk["kernel"]))
 
     def rhs(v):
         if chk.get("kmax"):
@@ -287,6 +289,83 @@ def cpu_legs(c, budget_s: float, checks: dict, log=print):
     return out
 
 
+def tensor_train_lines(agg, synth, torch, np, checks, log):
+    """Kernels in tensor-train form (Sec. 2) through the per-bin matrix chain
+    (agg_plan_create_tt), D=4, N=65536, 20 Heun steps of one state:
+    random dense cores of ranks (1,3,1), (1,4,4,1), (1,6,6,6,1) against the
+    same kernel as rank paths (agg_tt_expand: 3 + 16 + 216 rank-one terms);
+    and the ballistic kernel at orders 2 and 3 (no CP or TT form known)
+    compressed by agg_tt_cross to ranks <= 8."""
+    h, steps = 1e-6, 20
+    out = {}
+    for N in (4096, 65536):
+        rng = np.random.default_rng(80)
+        cores = lambda ranks: [rng.uniform(0.1, 1.0, size=(ranks[m], N, ranks[m + 1]))
+                               for m in range(len(ranks) - 1)]
+        tt = {2: cores([1, 3, 1]), 3: cores([1, 4, 4, 1]), 4: cores([1, 6, 6, 6, 1])}
+        n0 = synth.n0_uniform_head(N, 3, 16)
+        rates, refused = {}, None
+        for prec in ("fp64", "fp32c"):
+            for how in ("chain", "paths"):
+                try:
+                    if how == "chain":
+                        plan = agg.Plan(4, N, prec=prec, tt=tt)
+                    else:
+                        plan = agg.Plan(4, N, {d: agg.tt_expand(N, c) for d, c in tt.items()}, prec)
+                except agg.AggError as e:
+                    refused = str(e)
+                    log(f"[bench] TT ranks 6 D=4 N={N} {how} {prec}: refused ({e})")
+                    continue
+                n = torch.tensor(n0, dtype=torch.float64, device="cuda:0")
+                t, _ = time_steps(plan, n, h, steps, 2, torch)
+                rates[f"{how}_{prec}"] = round(2 * steps / t, 1)
+                if how == "chain":
+                    f = plan.rhs(torch.tensor(n0, dtype=torch.float64, device="cuda:0"))
+                    checks[f"tt_chain_ranks6_n{N}_rhs_{prec}"] = (
+                        f.cpu().numpy(), dict(kind="rhs", D=4, N=N, tt=tt, n=n0, kmax=64))
+                plan.close()
+                del n
+                log(f"[bench] TT ranks 6 D=4 N={N} {how} {prec}: {rates[f'{how}_{prec}']} RHS/s")
+        out[f"ranks6_n{N}"] = {
+            "workload": f"D=4 N={N}, random dense TT cores ranks (1,3,1),(1,4,4,1),(1,6,6,6,1) (114 core "
+                        "columns), n0 uniform on [1,16], 20 Heun steps h=1e-6; chain = agg_plan_create_tt, "
+                        "paths = the same kernel as 3+16+216 rank-one terms (agg_tt_expand)",
+            "rhs_per_s": rates,
+            "chain_vs_paths": {p: round(rates[f"chain_{p}"] / rates[f"paths_{p}"], 3)
+                               for p in ("fp64", "fp32c") if f"paths_{p}" in rates and f"chain_{p}" in rates},
+            "paths_refused": refused}
+    N = 65536
+    n0 = synth.n0_uniform_head(N, 3, 16)
+
+    def ballistic(a):
+        s = a.astype(np.float64)
+        return np.sum(s ** (1 / 3), axis=1) ** 2 * np.sqrt(np.sum(1.0 / s, axis=1))
+    t0 = time.perf_counter()
+    cross = {d: agg.tt_cross(d, N, ballistic, tol=1e-12, rmax=8, seed=d) for d in (2, 3)}
+    tcross = time.perf_counter() - t0
+    ttb = {d: c for d, (c, _) in cross.items()}
+    rates = {}
+    for prec in ("fp64", "fp32c"):
+        plan = agg.Plan(3, N, prec=prec, tt=ttb)
+        n = torch.tensor(n0, dtype=torch.float64, device="cuda:0")
+        t, _ = time_steps(plan, n, h, steps, 2, torch)
+        rates[prec] = round(2 * steps / t, 1)
+        f = plan.rhs(torch.tensor(n0, dtype=torch.float64, device="cuda:0"))
+        checks[f"tt_cross_ballistic_rhs_{prec}"] = (f.cpu().numpy(), dict(kind="rhs", D=3, N=N, tt=ttb,
+                                                                          n=n0, kmax=48))
+        plan.close()
+        del n
+        log(f"[bench] TT-cross ballistic D=3 N={N} {prec}: {rates[prec]} RHS/s")
+    out["tt_cross_ballistic"] = {
+        "workload": "D=3 N=65536, kernel (sum_m i_m^(1/3))^2 (sum_m 1/i_m)^(1/2) at orders 2 and 3, "
+                    "compressed on the host by agg_tt_cross (rmax 8), n0 uniform on [1,16], 20 Heun steps h=1e-6",
+        "ranks": {d: [1] + [int(x.shape[2]) for x in c] for d, (c, _) in cross.items()},
+        "cross_err_est": {d: float(f"{e:.3e}") for d, (_, e) in cross.items()},
+        "cross_seconds": round(tcross, 2),
+        "rhs_per_s": rates}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +380,8 @@ def main():
                     help="run the D=3 pure ternary N=2^19 tensor-train kernel line (0 = skip)")
     ap.add_argument("--c5b", type=int, default=64,
                     help="states of the D=5 N=2^20 compressed (sum i)^(1/2) line (0 = skip)")
+    ap.add_argument("--tt", type=int, default=1,
+                    help="run the tensor-train lines (matrix chain vs rank paths; TT-cross kernel) (0 = skip)")
     ap.add_argument("--quick", action="store_true",
                     help="profiling aid: time only the primary precision (on --batch states if > 0), "
                          "no pass timing, no other lines")
@@ -490,6 +571,10 @@ def main():
         del n
         torch.cuda.empty_cache()
 
+    tt_lines = None
+    if args.tt:
+        tt_lines = tensor_train_lines(agg, synth, torch, np, checks, log)
+
     prim = results[args.prec]
     cs = PREC_BYTES[args.prec]
     # dominant kernel of a time step: the pass with the largest device time
@@ -554,6 +639,7 @@ def main():
         "d5_n2e20_batch64_rhs_per_s": c5 or None,
         "d5_n2e20_sqrt_sum_kernel_rhs_per_s": c5b,
         "paper_table1_shape": table1,
+        "tensor_train": tt_lines,
         "ratio_fp32c_vs_plain_fp64": round(results["fp32c"]["rhs_per_s"] / plain_rate, 3),
         "pass_us": {p: {PASS_NAMES[w]: round(v, 3) for w, v in r["passes_us"].items()} for p, r in results.items()},
         "roofline": roofline,
