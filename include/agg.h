@@ -59,9 +59,18 @@ enum {
  * evaluates the right-hand side term by term, one rank-one term (d, r) at a
  * time with its own d transforms (no column shared, not even equal ones),
  * accumulating f, with separate forward, row, inverse and Heun launches per
- * stage: the unshared, unfused reference evaluation. */
+ * stage: the unshared, unfused reference evaluation.
+ * AGG_MIXED_RADIX may be OR-ed into the precision of agg_plan_create,
+ * agg_plan_tables and agg_submit: the transform length may then be 3 2^a or
+ * 5 2^a (radix-3 or radix-5 first stage in the column transforms) when that is
+ * shorter than the power of two, e.g. 5 2^20 instead of 2^23 for D = 5,
+ * N = 2^20 (37.5% fewer spectral bytes): the smallest 3 2^a or 5 2^a (a >= 4)
+ * at least D_e N - 1, kept when its two-pass split has a column length in
+ * {96, 192, 384, 768, 1536} or {160, 320, 640, 1280}, else the power of two.
+ * It is not combined with AGG_PLAIN. */
 typedef enum { AGG_FP64 = 0, AGG_FP32 = 1, AGG_FP32C = 2 } agg_precision;
 #define AGG_PLAIN 0x100
+#define AGG_MIXED_RADIX 0x200
 
 /* One collision order d: C^(d) = sum_r weight[r] prod_m U_m(i_m, r).
  * U[m-1] is a HOST pointer to N*rank doubles, column-major by rank:
@@ -225,7 +234,8 @@ agg_status agg_profile_pass(agg_plan* plan, const double* n, int32_t pass, int32
  *  per chunk: ncols, nterms, column ids[ncols], gain-term indices[nterms]])
  * into out[0..cap) and its full length into *len.  AGG_EINVAL if cap is short
  * (len still set).  agg_twiddles writes exp(-2 pi i e / P) for e = 0..P-1 as
- * interleaved binary64 (re, im) pairs into out[0..2P) (P a power of two). */
+ * interleaved binary64 (re, im) pairs into out[0..2P): P a power of two, or
+ * 3 2^k or 5 2^k with k >= 3 (the mixed-radix lengths); AGG_EINVAL otherwise. */
 agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
                            int32_t prec, int64_t* out, int64_t cap, int64_t* len);
 agg_status agg_twiddles(int64_t P, double* out);

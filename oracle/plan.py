@@ -32,6 +32,21 @@ P8  Row-pass chunks, only when u*2*(M2 + M2/16)*cs + (M2 <= 512 ? M2*cs : 0)
     single term has more than cmax distinct ids.  A chunk lists its ids
     ascending and its terms by P4 position, in visiting order.
 
+With the mixed-radix option (transform lengths 3 2^a and 5 2^a):
+
+X2  L' = the smaller of the smallest 48*2^k and the smallest 80*2^k (k >= 0)
+    that are >= De*N - 1.  Only when L' < L (P2) is it tried; else P2/P6/P7.
+X6  With M = L'/2 = o 2^m (o = 3 or 5): M2 = largest power of two with M2^2
+    <= M, M1 = M/M2.  While M1 > M1max (1536 for o = 3, 1280 for o = 5) and
+    2*o divides M1: halve M1, double M2.  Then while u*2*M2*cs > 64 KiB,
+    2*M1 <= M1max and M2 >= 4: double M1, halve M2.  The split is kept when
+    M1 lies in [M1min, M1max] (M1min 96 for o = 3, 160 for o = 5), o divides
+    M1, M2 >= 2, and 2^b divides L' with b = ceil(ceil(log2 L')/2) (the
+    two-level table of w_L' splits the exponent at bit b); otherwise L, P6
+    and P7 are used as without the option.
+X7  g = the largest power of two <= min(M2, max(1, floor(1024 / M1))).
+P8 applies unchanged with the M2 of X6.
+
 Flat table (int64), as exported for comparison:
     [L, M1, M2, g, u, Tp, Tq, De,
      colmap in scan order (one id per (d, m, r)),
@@ -55,7 +70,36 @@ def _log2_exact(x: int) -> int:
     return x.bit_length() - 1
 
 
-def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = True):
+def _ceil_log2(x: int) -> int:
+    return (x - 1).bit_length()
+
+
+def _mixed_split(L: int, u: int, cs: int):
+    """X6/X7 for a length L' = o 2^a: (M1, M2, g), or None when unsupported."""
+    o = 3 if L % 3 == 0 else 5
+    M = L // 2
+    M1max, M1min = (1536, 96) if o == 3 else (1280, 160)
+    M2 = 1
+    while (2 * M2) ** 2 <= M:
+        M2 *= 2
+    M1 = M // M2
+    while M1 > M1max and M1 % (2 * o) == 0:
+        M1 //= 2
+        M2 *= 2
+    while u * 2 * M2 * cs > 65536 and 2 * M1 <= M1max and M2 >= 4:
+        M1 *= 2
+        M2 //= 2
+    b = (_ceil_log2(L) + 1) // 2
+    if not (M1min <= M1 <= M1max and M1 % o == 0 and M2 >= 2 and L % (1 << b) == 0):
+        return None
+    cap = min(M2, max(1, 1024 // M1))
+    g = 1
+    while 2 * g <= cap:
+        g *= 2
+    return M1, M2, g
+
+
+def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = True, mixed: bool = False):
     ranks = {d: (kernel[d].shape[1] if d in kernel else 0) for d in range(2, D + 1)}
     De = max([d for d in range(2, D + 1) if ranks[d] > 0], default=2)
     L = 1
@@ -95,17 +139,33 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = 
     qterms = sorted(qt.items(), key=lambda kv: kv[0])
 
     cs = PREC_BYTES[prec]
-    lg = _log2_exact(M)
-    M1 = 1 << ((lg + 1) // 2)
-    M2 = M // M1
-    while u * 2 * M2 * cs > 65536 and M1 < 2048:
-        M1 *= 2
-        M2 //= 2
-    if M1 > 2048:
-        raise Unsupported(f"no two-pass split for L={L}")
-    if M2 < 2:
-        raise Unsupported(f"u={u} distinct columns leave rows of one value at L={L}")
-    g = min(M2, max(1, 1024 // M1))
+    split = None
+    if mixed:
+        Lm = None
+        for base in (48, 80):
+            c = base
+            while c < De * N - 1:
+                c *= 2
+            if Lm is None or c < Lm:
+                Lm = c
+        if Lm < L:
+            split = _mixed_split(Lm, u, cs)
+            if split is not None:
+                L, M = Lm, Lm // 2
+    if split is not None:
+        M1, M2, g = split
+    else:
+        lg = _log2_exact(M)
+        M1 = 1 << ((lg + 1) // 2)
+        M2 = M // M1
+        while u * 2 * M2 * cs > 65536 and M1 < 2048:
+            M1 *= 2
+            M2 //= 2
+        if M1 > 2048:
+            raise Unsupported(f"no two-pass split for L={L}")
+        if M2 < 2:
+            raise Unsupported(f"u={u} distinct columns leave rows of one value at L={L}")
+        g = min(M2, max(1, 1024 // M1))
 
     chunks = []
     if u * 2 * (M2 + M2 // 16) * cs + (M2 * cs if M2 <= 512 else 0) > 147456:

@@ -12,7 +12,7 @@ def twiddles_ref(P: int, idx=None):
         idx = range(P)
     out = np.empty((len(idx), 2), dtype=np.float64)
     for j, e in enumerate(idx):
-        a = mpmath.mpf(-2 * int(e)) / P        # exact: P is a power of two
+        a = mpmath.mpf(-2 * int(e)) / P        # exact for P = 2^k; else to 60 digits
         out[j, 0] = float(mpmath.cospi(a))     # cos(pi a), exact zeros at multiples of 1/2
         out[j, 1] = float(mpmath.sinpi(a))
     return out

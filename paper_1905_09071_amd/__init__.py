@@ -93,13 +93,19 @@ def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64") -> np.ndarray:
 
 
 AGG_PLAIN = 0x100
+AGG_MIXED_RADIX = 0x200
 
 
-def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", plain: bool = False) -> np.ndarray:
+def _plan_code(prec: str, plain: bool, mixed: bool) -> int:
+    return PREC[prec] | (AGG_PLAIN if plain else 0) | (AGG_MIXED_RADIX if mixed else 0)
+
+
+def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", plain: bool = False,
+                mixed: bool = False) -> np.ndarray:
     """The planner's integer tables (host only, no device touched)."""
     terms, nt, keep = make_terms(D, N, kernel)
     ln = ctypes.c_int64(0)
-    code = PREC[prec] | (AGG_PLAIN if plain else 0)
+    code = _plan_code(prec, plain, mixed)
     lib().agg_plan_tables(D, N, terms, nt, code, None, 0, ctypes.byref(ln))
     out = np.zeros(max(ln.value, 1), dtype=np.int64)
     check(lib().agg_plan_tables(D, N, terms, nt, code,
@@ -195,22 +201,23 @@ class Plan:
     """agg_plan: a kernel set, precision and batch size bound to a stream."""
 
     def __init__(self, D: int, N: int, kernel: dict = None, prec: str = "fp64", batch: int = 1, stream=None,
-                 plain: bool = False, tt: dict = None):
+                 plain: bool = False, tt: dict = None, mixed: bool = False):
         """plain=True: the term-by-term, unshared, unfused reference evaluation.
         tt={d: cores}: the kernel set in tensor-train form instead of CP factors
-        (agg_plan_create_tt)."""
+        (agg_plan_create_tt).  mixed=True: transform lengths 3 2^a and 5 2^a
+        allowed (AGG_MIXED_RADIX)."""
         self.D, self.N, self.batch, self.prec, self.plain = D, N, batch, prec, plain
         self._stream = stream
         h = ctypes.c_void_p()
         if tt is not None:
-            if kernel is not None or plain:
-                raise ValueError("a tensor-train plan takes no CP kernel and no plain option")
+            if kernel is not None or plain or mixed:
+                raise ValueError("a tensor-train plan takes no CP kernel and no plain or mixed option")
             terms, nt, keep = make_tt_terms(D, N, tt)
             check(lib().agg_plan_create_tt(D, N, terms, nt, PREC[prec], batch, _stream_handle(stream),
                                            ctypes.byref(h)))
         else:
             terms, nt, keep = make_terms(D, N, kernel)
-            code = PREC[prec] | (AGG_PLAIN if plain else 0)
+            code = _plan_code(prec, plain, mixed)
             check(lib().agg_plan_create(D, N, terms, nt, code, batch, _stream_handle(stream),
                                         ctypes.byref(h)))
         del keep
@@ -284,14 +291,14 @@ class Engine:
         except Exception:
             pass
 
-    def submit(self, D, N, kernel, n0, dt, t_end, prec="fp32c") -> int:
+    def submit(self, D, N, kernel, n0, dt, t_end, prec="fp32c", mixed: bool = False) -> int:
         terms, nt, keep = make_terms(D, N, kernel)
         n0 = np.ascontiguousarray(n0, dtype=np.float64)
         if n0.size != N:
             raise ValueError("n0 must have N entries")
         t = ctypes.c_uint64(0)
         check(lib().agg_submit(self._h, D, N, terms, nt, n0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                               float(dt), float(t_end), PREC[prec], ctypes.byref(t)))
+                               float(dt), float(t_end), _plan_code(prec, False, mixed), ctypes.byref(t)))
         del keep
         return t.value
 

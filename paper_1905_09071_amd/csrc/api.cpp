@@ -396,7 +396,10 @@ extern "C" {
 const char* agg_last_error(void) { return g_err.c_str(); }
 
 agg_status agg_twiddles(int64_t P, double* out) {
-  if (P < 1 || (P & (P - 1)) != 0 || !out) return set_error(AGG_EINVAL, "P must be a power of two");
+  int64_t odd = P;
+  while (odd > 0 && odd % 2 == 0) odd /= 2;
+  const bool ok = P >= 1 && (odd == 1 || ((odd == 3 || odd == 5) && P % (8 * odd) == 0));
+  if (!ok || !out) return set_error(AGG_EINVAL, "P must be 2^k, 3 2^k or 5 2^k (k >= 3)");
   twiddle_table(P, out);
   return AGG_OK;
 }
@@ -406,8 +409,10 @@ agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t 
   PlanTables T;
   std::string err;
   const int opt = (int)prec;
-  if ((opt & ~(0xff | AGG_PLAIN)) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
-  agg_status rc = plan_build(D, N, terms, nterms, opt & 0xff, &T, &err, !(opt & AGG_PLAIN));
+  if ((opt & ~(0xff | AGG_PLAIN | AGG_MIXED_RADIX)) != 0 || ((opt & AGG_PLAIN) && (opt & AGG_MIXED_RADIX)))
+    return set_error(AGG_EINVAL, "unknown plan option bits");
+  agg_status rc = plan_build(D, N, terms, nterms, opt & 0xff, &T, &err, !(opt & AGG_PLAIN),
+                             (opt & AGG_MIXED_RADIX) != 0);
   if (rc != AGG_OK) return set_error(rc, err);
   if (len) *len = (int64_t)T.flat.size();
   if (!out || cap < (int64_t)T.flat.size()) return set_error(AGG_EINVAL, "output capacity too small");
@@ -418,11 +423,12 @@ agg_status agg_plan_tables(int32_t D, int64_t N, const agg_term* terms, int32_t 
 static agg_status plan_create_from(agg_plan* p, int32_t batch, void* hip_stream, agg_plan** out);
 
 static agg_status plan_create_impl(int32_t D, int64_t N, const agg_term* terms, int32_t nterms, int prec,
-                                   int32_t batch, void* hip_stream, bool dedup, agg_plan** out) {
+                                   int32_t batch, void* hip_stream, bool dedup, agg_plan** out,
+                                   bool mixed = false) {
   *out = nullptr;
   agg_plan* p = new agg_plan();
   std::string err;
-  agg_status rc = plan_build(D, N, terms, nterms, prec, &p->tab, &err, dedup);
+  agg_status rc = plan_build(D, N, terms, nterms, prec, &p->tab, &err, dedup, mixed);
   if (rc != AGG_OK) { delete p; return set_error(rc, err); }
   return plan_create_from(p, batch, hip_stream, out);
 }
@@ -484,8 +490,10 @@ agg_status agg_plan_create(int32_t D, int64_t N, const agg_term* terms, int32_t 
   if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");
   const int opt = (int)prec_opt;
   const int prec = opt & 0xff;
-  if ((opt & ~(0xff | AGG_PLAIN)) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
-  if (!(opt & AGG_PLAIN)) return plan_create_impl(D, N, terms, nterms, prec, batch, hip_stream, true, out);
+  if ((opt & ~(0xff | AGG_PLAIN | AGG_MIXED_RADIX)) != 0 || ((opt & AGG_PLAIN) && (opt & AGG_MIXED_RADIX)))
+    return set_error(AGG_EINVAL, "unknown plan option bits");
+  if (!(opt & AGG_PLAIN))
+    return plan_create_impl(D, N, terms, nterms, prec, batch, hip_stream, true, out, (opt & AGG_MIXED_RADIX) != 0);
 
   // term-by-term reference evaluation: validate the whole set, then one
   // sub-plan per rank-one term (d, r) with no column sharing
@@ -587,6 +595,10 @@ static void drop_graph(agg_plan* p) {
 // replayed on the plan's stream.  It holds kernel nodes only.
 static agg_status step_graph(agg_plan* p, double* n, double h) {
   if (p->gexec && p->g_state == n && p->g_dt == h) return AGG_OK;
+  // launches of the graph being replaced may still run (a solve without
+  // statistics returns before the device is done): the executable graph must
+  // outlive them
+  if (p->gexec) (void)hipStreamSynchronize(p->stream);
   drop_graph(p);
   hipError_t e = hipSuccess;
   if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);

@@ -12,15 +12,16 @@
 // its arithmetic depends on its neighbours (every launch variant runs the same
 // stage sequence).
 //
-// The ticks are replayed from a captured hipGraph (several ticks per graph
-// launch).  The launches read their bucket's slot table and its list of active
-// entries from device memory, with a grid sized for a power-of-two capacity
-// (workgroups past the active list exit at once), so admissions and
-// retirements only rewrite that list between graph launches: the graph is
-// captured again only when the set of buckets, a bucket's capacity or its
-// table maxima change.  With several buckets each one runs on one of a few
-// lane streams (forked from and joined back into the scheduler's stream inside
-// the graph), letting small launches of different lengths share the GPU.
+// The host enqueues ticks in groups of four.  The launches read their bucket's
+// slot table and its list of active entries from device memory, with a grid
+// sized for a power-of-two capacity (workgroups past the active list exit at
+// once), so admissions and retirements only rewrite that list between groups,
+// and the launch arguments change only when the set of buckets, a bucket's
+// capacity or its table maxima change (the condition under which a captured
+// graph of the group, which the engine can replay instead, would be captured
+// again; see kCaptureTicks).  With several buckets each one runs on one of a
+// few lane streams (forked from and joined back into the scheduler's stream),
+// letting small launches of different lengths share the GPU.
 //
 // Memory: the engine owns one device region (its budget) and one pinned host
 // region, each carved by a first-fit allocator.  A request holds one
@@ -207,6 +208,12 @@ struct Engine {
   int64_t* d_tick = nullptr;         // device tick counter (start of the device region)
   int64_t host_tick = 0;             // ticks enqueued so far
   static constexpr int kTicksPerGraph = 4;
+  // Ticks replayed from a captured graph (rebuild_graph) instead of launched
+  // directly.  Off: with several buckets (lane streams forked and joined by
+  // events inside the capture) a serving run ended in a segmentation fault in a
+  // thread of the process other than the caller's, whose cause was not found;
+  // direct launches run the same kernels on the same tick schedule.
+  static constexpr bool kCaptureTicks = false;
   hipGraphExec_t gexec = nullptr;
   bool graph_stale = true;
   // replaced graphs, destroyed once the device has passed their last launch
@@ -577,10 +584,30 @@ hipError_t Engine::rebuild_graph() {
   return e;
 }
 
-// Enqueues the next ticks: a graph launch, with at most kInFlight of them
-// ahead of the device.
+// Enqueues the next kTicksPerGraph ticks, with at most kInFlight such groups
+// ahead of the device: launched directly, or (kCaptureTicks) as one launch of
+// the captured graph.
 hipError_t Engine::launch_ticks() {
   hipError_t e = hipSuccess;
+  if (!kCaptureTicks) {
+    if (graph_stale) {   // launch capacities follow the membership
+      for (auto& kv : buckets) {
+        Bucket& b = *kv.second;
+        b.cap = b.order.empty() ? 0 : pow2_at_least((int)b.order.size());
+      }
+      graph_stale = false;
+    }
+    if (launch_used[launch_pos]) (void)hipEventSynchronize(launch_ev[launch_pos]);
+    for (int t = 0; t < kTicksPerGraph && e == hipSuccess; ++t) {
+      e = enqueue_tick();
+      if (e == hipSuccess) host_tick += 1;
+    }
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(launch_ev[launch_pos], stream);
+    launch_used[launch_pos] = true;
+    launch_pos = (launch_pos + 1) % kInFlight;
+    return e;
+  }
   if (graph_stale) {
     e = rebuild_graph();
     if (e != hipSuccess) return e;
@@ -770,7 +797,8 @@ agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms
   if (!(t_end >= 0.0) || !std::isfinite(t_end)) return set_error(AGG_EINVAL, "t_end must be finite and >= 0");
   auto r = std::make_unique<Request>();
   std::string err;
-  agg_status rc = plan_build(D, N, terms, nterms, prec, &r->tab, &err);
+  if ((prec & ~(0xff | AGG_MIXED_RADIX)) != 0) return set_error(AGG_EINVAL, "unknown precision option bits");
+  agg_status rc = plan_build(D, N, terms, nterms, prec & 0xff, &r->tab, &err, true, (prec & AGG_MIXED_RADIX) != 0);
   if (rc != AGG_OK) return set_error(rc, err);
   if (r->tab.u == 0) return set_error(AGG_EINVAL, "the engine needs at least one term with rank > 0");
   for (int64_t i = 0; i < N; ++i)

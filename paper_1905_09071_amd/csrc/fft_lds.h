@@ -1,4 +1,5 @@
-// Batched power-of-two FFTs held in LDS, for one workgroup of NT threads.
+// Batched FFTs of lengths 2^k, 3 2^k and 5 2^k held in LDS, for one
+// workgroup of NT threads.
 //
 // Stockham autosort formulation: stage s with radix R and span NS (product of
 // the radices before it) takes butterfly b (0 <= b < P/R) from positions
@@ -80,10 +81,61 @@ template <class T, int DIR> __device__ __forceinline__ void dft8(cplx<T>* v) {
   v[7] = csub(e[3], t3);
 }
 
+// multiplication by DIR * i
+template <class T, int DIR> __device__ __forceinline__ cplx<T> mul_dir_i(cplx<T> x) {
+  return DIR < 0 ? cmul_negi(x) : cmul_i(x);
+}
+
+// Length-3 DFT: y_0 = x_0 + a, y_{1,2} = x_0 - a/2 +- DIR i (sqrt(3)/2) b with
+// a = x_1 + x_2, b = x_1 - x_2 (the roots w^1, w^2 = -1/2 +- DIR i sqrt(3)/2).
+template <class T, int DIR> __device__ __forceinline__ void dft3(cplx<T>* v) {
+  const T h = Real<T>::from_d(0.5);
+  const T s3 = Real<T>::from_d(0.86602540378443864676372317075293618347);   // sqrt(3)/2
+  const cplx<T> a = cadd(v[1], v[2]), b = csub(v[1], v[2]);
+  const cplx<T> m = csub(v[0], cscale(a, h));
+  const cplx<T> t = mul_dir_i<T, DIR>(cscale(b, s3));
+  v[0] = cadd(v[0], a);
+  v[1] = cadd(m, t);
+  v[2] = csub(m, t);
+}
+
+// Length-5 DFT from the symmetric sums a_1 = x_1 + x_4, a_2 = x_2 + x_3 and
+// differences b_1 = x_1 - x_4, b_2 = x_2 - x_3, with c_k = cos(2 pi k/5),
+// s_k = sin(2 pi k/5):
+//   y_0 = x_0 + a_1 + a_2
+//   y_{1,4} = x_0 + c_1 a_1 + c_2 a_2 +- DIR i (s_1 b_1 + s_2 b_2)
+//   y_{2,3} = x_0 + c_2 a_1 + c_1 a_2 +- DIR i (s_2 b_1 - s_1 b_2)
+template <class T, int DIR> __device__ __forceinline__ void dft5(cplx<T>* v) {
+  const T c1 = Real<T>::from_d(0.30901699437494742410229341718281905886);
+  const T c2 = Real<T>::from_d(-0.80901699437494742410229341718281905886);
+  const T s1 = Real<T>::from_d(0.95105651629515357211643933337938214340);
+  const T s2 = Real<T>::from_d(0.58778525229247312916870595463907276860);
+  const cplx<T> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  const cplx<T> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  const cplx<T> m1 = cadd(v[0], cadd(cscale(a1, c1), cscale(a2, c2)));
+  const cplx<T> m2 = cadd(v[0], cadd(cscale(a1, c2), cscale(a2, c1)));
+  const cplx<T> t1 = mul_dir_i<T, DIR>(cadd(cscale(b1, s1), cscale(b2, s2)));
+  const cplx<T> t2 = mul_dir_i<T, DIR>(csub(cscale(b1, s2), cscale(b2, s1)));
+  v[0] = cadd(v[0], cadd(a1, a2));
+  v[1] = cadd(m1, t1);
+  v[4] = csub(m1, t1);
+  v[2] = cadd(m2, t2);
+  v[3] = csub(m2, t2);
+}
+
 template <class T, int R, int DIR> __device__ __forceinline__ void dftR(cplx<T>* v) {
   if constexpr (R == 2) dft2<T, DIR>(v);
+  else if constexpr (R == 3) dft3<T, DIR>(v);
   else if constexpr (R == 4) dft4<T, DIR>(v);
+  else if constexpr (R == 5) dft5<T, DIR>(v);
   else dft8<T, DIR>(v);
+}
+
+// Radix of the stage at span NS of a length-P transform with largest
+// power-of-two radix RMAX: lengths 3 2^k and 5 2^k take their odd factor in
+// the first stage, then powers of two (radix RMAX while at least RMAX remains).
+__host__ __device__ constexpr int stage_radix(int P, int NS, int RMAX) {
+  return (NS == 1 && P % 5 == 0) ? 5 : (NS == 1 && P % 3 == 0) ? 3 : (P / NS >= RMAX ? RMAX : P / NS);
 }
 
 // One Stockham stage over `nfft` transforms (nfft <= NB) stored at stride STR.
@@ -166,15 +218,14 @@ __device__ __forceinline__ void fft_stage_pp(const cplx<T>* src, cplx<T>* dst, i
 // from span NS0 on.
 __host__ __device__ constexpr int fft_nstages(int P, int RMAX, int NS0 = 1) {
   int n = 0;
-  for (int ns = NS0; ns < P; ns *= (P / ns >= RMAX ? RMAX : P / ns)) ++n;
+  for (int ns = NS0; ns < P; ns *= stage_radix(P, ns, RMAX)) ++n;
   return n;
 }
 
 template <class T, int P, int NS, int DIR, int NB, int STR, int NT, int RMAX>
 __device__ __forceinline__ void fft_stages_pp(cplx<T>* a, cplx<T>* b, int nfft, const cplx<T>* __restrict__ tw) {
   if constexpr (NS < P) {
-    constexpr int REM = P / NS;
-    constexpr int R = REM >= RMAX ? RMAX : REM;
+    constexpr int R = stage_radix(P, NS, RMAX);
     fft_stage_pp<T, P, R, NS, DIR, NB, STR, NT>(a, b, nfft, tw);
     fft_stages_pp<T, P, NS * R, DIR, NB, STR, NT, RMAX>(b, a, nfft, tw);
   }
@@ -183,8 +234,7 @@ __device__ __forceinline__ void fft_stages_pp(cplx<T>* a, cplx<T>* b, int nfft, 
 template <class T, int P, int NS, int DIR, int NB, int STR, int NT, int RMAX>
 __device__ __forceinline__ void fft_stages(cplx<T>* buf, int nfft, const cplx<T>* __restrict__ tw) {
   if constexpr (NS < P) {
-    constexpr int REM = P / NS;
-    constexpr int R = REM >= RMAX ? RMAX : REM;
+    constexpr int R = stage_radix(P, NS, RMAX);
     fft_stage<T, P, R, NS, DIR, NB, STR, NT>(buf, nfft, tw);
     fft_stages<T, P, NS * R, DIR, NB, STR, NT, RMAX>(buf, nfft, tw);
   }

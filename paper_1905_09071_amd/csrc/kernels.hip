@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   for (int it = 0; it < IPT; ++it) {
     int idx = tid + it * NT;
     int k1 = idx >> lgg, jl = idx & (g - 1);
-    int64_t e = (2 * (int64_t)(j2_0 + jl) * k1) & (a.L - 1);
+    int64_t e = (2 * (int64_t)(j2_0 + jl) * k1) % a.L;
     bool ok = fwd && idx < nitems;
     wsh[it] = ok ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
     wsl[it] = ok ? ldg((const cplx<T>*)a.twLlo + (e & ((int64_t(1) << a.b) - 1))) : czero<T>();
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   // of the group's columns lies in the first block of the first radix-R1 stage
   // (j1 < M1/R1), that stage only copies each input to its R1 outputs: the
   // weighting writes them directly and the transform starts at its second stage.
-  constexpr int R1 = StageRadix<T, M1>::value < M1 ? StageRadix<T, M1>::value : M1;
+  constexpr int R1 = stage_radix(M1, 1, StageRadix<T, M1>::value);   // radix of the first stage
   const int64_t rest = N - 2 * (int64_t)j2_0;
   const bool prune = kColPrune<T, LEAN> && !CWAVE && (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
   auto put = [&](int slot, int j1, cplx<T> v) {
@@ -643,7 +643,7 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
       // wavefront transforms: wavefront rr stores row rr, lane l value e is j2 = l + 64 e
       int idx = WAVE ? wave * M2 + lane + 64 * i : tid + i * NT;
       int rr = idx / M2, j2 = idx - rr * M2;
-      int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) & (a.L - 1);
+      int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) % a.L;
       wvh[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLhi + (e >> a.b)) : czero<T>();
       wvl[i] = idx < nrows * M2 ? ldg((const cplx<T>*)a.twLlo + (e & lmask)) : czero<T>();
     }
@@ -1112,7 +1112,7 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
     const int idx = tid + i * NT;
     if (idx < nrows * M2) {
       const int rr = idx / M2, j2 = idx - rr * M2;
-      const int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) & (a.L - 1);
+      const int64_t e = (2 * (int64_t)j2 * row_of(rr == 1)) % a.L;
       stg(V + ((int64_t)row_of(rr) * M2 + j2), cnorm(cmulc(X[rr * STR + lds_pad(j2)], twL<T>(a, e))));
     }
   }
@@ -1323,6 +1323,16 @@ static hipError_t launch_col_p(const LaunchArgs& a, hipStream_t s) {
     case 512: return launch_col_t<T, 512>(a, s);
     case 1024: return launch_col_t<T, 1024>(a, s);
     case 2048: return launch_col_t<T, 2048>(a, s);
+    // mixed-radix lengths (the planner's supported set)
+    case 96: return launch_col_t<T, 96>(a, s);
+    case 192: return launch_col_t<T, 192>(a, s);
+    case 384: return launch_col_t<T, 384>(a, s);
+    case 768: return launch_col_t<T, 768>(a, s);
+    case 1536: return launch_col_t<T, 1536>(a, s);
+    case 160: return launch_col_t<T, 160>(a, s);
+    case 320: return launch_col_t<T, 320>(a, s);
+    case 640: return launch_col_t<T, 640>(a, s);
+    case 1280: return launch_col_t<T, 1280>(a, s);
   }
   return hipErrorInvalidValue;
 }

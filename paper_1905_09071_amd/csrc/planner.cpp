@@ -62,8 +62,32 @@ static agg_status split_pass(PlanTables& P, std::string* err) {
   return AGG_OK;
 }
 
+// Mixed-radix split of M = L/2 = odd 2^m (odd 3 or 5): M2 the largest power
+// of two with M2^2 <= M, M1 = M/M2 (carrying the odd factor); M1 halved
+// (M2 doubled) down to the largest supported column length, then doubled
+// while the row working set u*2*M2 complex values exceeds 64 KiB and M1 stays
+// supported.  False (the caller falls back to a power-of-two length) when M1
+// leaves the supported set or M2 < 2.
+static bool split_mixed(PlanTables& P, int odd) {
+  const int cs = complex_bytes(P.prec);
+  const int64_t maxM1 = odd == 3 ? 1536 : 1280, minM1 = odd == 3 ? 96 : 160;
+  int64_t M2 = 1;
+  while ((M2 * 2) * (M2 * 2) <= P.M) M2 *= 2;
+  int64_t M1 = P.M / M2;
+  while (M1 > maxM1 && M1 % (2 * odd) == 0) { M1 /= 2; M2 *= 2; }
+  while ((int64_t)P.u * 2 * M2 * cs > 65536 && M1 * 2 <= maxM1 && M2 >= 4) { M1 *= 2; M2 /= 2; }
+  if (M1 < minM1 || M1 > maxM1 || M2 < 2 || M1 % odd != 0) return false;
+  P.b = (ilog2(P.L) + 1) / 2;
+  if (P.L % (int64_t(1) << P.b) != 0) return false;
+  P.M1 = (int)M1; P.M2 = (int)M2;
+  int64_t g = 1;
+  while (g * 2 <= std::min<int64_t>(M2, std::max<int64_t>(1, 1024 / M1))) g *= 2;
+  P.g = (int)g;
+  return true;
+}
+
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
-                      PlanTables* out, std::string* err, bool dedup) {
+                      PlanTables* out, std::string* err, bool dedup, bool mixed) {
   if (D < 2 || D > AGG_MAX_D) { *err = "D must lie in [2, AGG_MAX_D]"; return AGG_EINVAL; }
   if (N < 1) { *err = "N must be >= 1"; return AGG_EINVAL; }
   if (prec != AGG_FP64 && prec != AGG_FP32 && prec != AGG_FP32C) {
@@ -103,6 +127,16 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   while (L < De * N - 1) L *= 2;
   L = std::max<int64_t>(L, 16);
   P.L = L; P.M = L / 2;
+  // mixed radix: the smallest of 3 2^a, 5 2^a (a >= 4) at least De N - 1 when
+  // it is shorter than the power of two
+  int odd = 1;
+  int64_t Lmix = L;
+  if (mixed)
+    for (int o : {3, 5}) {
+      int64_t c = 16 * o;
+      while (c < De * N - 1) c *= 2;
+      if (c < Lmix) { Lmix = c; odd = o; }
+    }
 
   // columns
   std::vector<const double*> uptr;
@@ -160,10 +194,19 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
     P.q_wsum.push_back(kv.second.second);
   }
 
-  // two-pass split
+  // two-pass split (mixed-radix length when its split is supported)
   const int cs = complex_bytes(prec);
-  agg_status src = split_pass(P, err);
-  if (src != AGG_OK) return src;
+  bool split_done = false;
+  if (odd > 1) {
+    P.L = Lmix; P.M = Lmix / 2;
+    split_done = split_mixed(P, odd);
+    if (!split_done) { P.L = L; P.M = L / 2; }
+  }
+  if (!split_done) {
+    agg_status src = split_pass(P, err);
+    if (src != AGG_OK) return src;
+  }
+  L = P.L;
   const int64_t M2 = P.M2;
 
   // chunks when the unchunked row pass's rows (at their padded LDS length) and

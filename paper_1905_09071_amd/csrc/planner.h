@@ -51,8 +51,10 @@ struct PlanTables {
 // code with a message in *err.
 // dedup = false gives every (d, m, r) column its own id (the unshared reference
 // evaluation); the rules are otherwise unchanged.
+// mixed = true: the transform length may be 3 2^a or 5 2^a (rules in
+// planner.cpp's split_mixed), with the odd factor in the column length.
 agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int prec,
-                      PlanTables* out, std::string* err, bool dedup = true);
+                      PlanTables* out, std::string* err, bool dedup = true, bool mixed = false);
 
 // The same for kernels given in tensor-train form: one agg_tt_term per order.
 // Adds to the rules of plan_build: column ids by first appearance scanning

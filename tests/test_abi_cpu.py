@@ -144,7 +144,8 @@ def test_invalid_arguments_refused_before_any_device_call():
     big = {4: np.ones((4, 1, Nbig))}
     assert _create(4, Nbig, big) == agg.AGG_EUNSUPPORTED
     assert b"2^23" in L.agg_last_error()
-    assert _create(3, 8, k, prec=0x200) == agg.AGG_EINVAL   # unknown option bit
+    assert _create(3, 8, k, prec=0x400) == agg.AGG_EINVAL   # unknown option bit
+    assert _create(3, 8, k, prec=0x300) == agg.AGG_EINVAL   # AGG_PLAIN with AGG_MIXED_RADIX
 
 
 def test_null_plan_calls_are_refused():
