@@ -491,24 +491,30 @@ def main():
             del n
             torch.cuda.empty_cache()
     c5 = {}
+    c5_mixed = {}
     if args.c5:
         cc = synth.config("C5a")
         B5 = cc["n0"].shape[0]
-        for prec in ("fp64", "fp32c"):
-            plan = agg.Plan(cc["D"], cc["N"], cc["kernel"], prec, batch=B5)
-            n = torch.tensor(cc["n0"].reshape(-1), dtype=torch.float64, device="cuda:0")
-            s5 = 10
-            t5, _ = time_steps(plan, n, cc["dt"], s5, 1, torch)
-            c5[prec] = round(2 * s5 * B5 / t5, 2)
-            f = plan.rhs(torch.tensor(cc["n0"].reshape(-1), dtype=torch.float64, device="cuda:0"))
-            f = f.cpu().numpy().reshape(B5, cc["N"])
-            for b in (0, B5 - 1):
-                checks[f"d5_n2e20_rhs_{prec}_member{b}"] = (
-                    f[b], dict(kind="rhs", D=cc["D"], N=cc["N"], kernel=cc["kernel"], n=cc["n0"][b], kmax=80))
-            log(f"[bench] D=5 N=2^20 batch {B5} {prec}: {s5} steps in {t5*1e3:.1f} ms -> {c5[prec]} RHS/s")
-            plan.close()
-            del n
-            torch.cuda.empty_cache()
+        # transform length 2^23, then (mixed-radix option) 5 2^20
+        for mixed, dst in ((False, c5), (True, c5_mixed)):
+            for prec in ("fp64", "fp32c"):
+                plan = agg.Plan(cc["D"], cc["N"], cc["kernel"], prec, batch=B5, mixed=mixed)
+                n = torch.tensor(cc["n0"].reshape(-1), dtype=torch.float64, device="cuda:0")
+                s5 = 10
+                t5, _ = time_steps(plan, n, cc["dt"], s5, 1, torch)
+                dst[prec] = round(2 * s5 * B5 / t5, 2)
+                f = plan.rhs(torch.tensor(cc["n0"].reshape(-1), dtype=torch.float64, device="cuda:0"))
+                f = f.cpu().numpy().reshape(B5, cc["N"])
+                tag = "_L5x2e20" if mixed else ""
+                for b in ((0, B5 - 1) if not mixed else (B5 - 1,)):
+                    checks[f"d5_n2e20{tag}_rhs_{prec}_member{b}"] = (
+                        f[b], dict(kind="rhs", D=cc["D"], N=cc["N"], kernel=cc["kernel"], n=cc["n0"][b], kmax=80))
+                L5 = int(agg.plan_tables(cc["D"], cc["N"], cc["kernel"], prec, mixed=mixed)[0])
+                log(f"[bench] D=5 N=2^20 batch {B5} {prec} L={L5}: {s5} steps in {t5*1e3:.1f} ms -> "
+                    f"{dst[prec]} RHS/s")
+                plan.close()
+                del n
+                torch.cuda.empty_cache()
 
     c5b = None
     if args.c5b:
@@ -556,6 +562,18 @@ def main():
         n = torch.tensor(synth.n0_uniform_head(N1, 3, 16), dtype=torch.float64, device="cuda:0")
         t1, _ = time_steps(plan, n, h1, s1, 1, torch)
         tab1 = agg.plan_tables(D1, N1, k1, "fp64")
+        # the same with the mixed-radix length 3 2^19
+        plan_m = agg.Plan(D1, N1, k1, "fp64", mixed=True)
+        n_m = torch.tensor(synth.n0_uniform_head(N1, 3, 16), dtype=torch.float64, device="cuda:0")
+        t1m, _ = time_steps(plan_m, n_m, h1, s1, 1, torch)
+        L1m = int(agg.plan_tables(D1, N1, k1, "fp64", mixed=True)[0])
+        nt1m = synth.n0_uniform_head(N1, 3, 16)
+        fm = plan_m.rhs(torch.tensor(nt1m, dtype=torch.float64, device="cuda:0"))
+        checks["table1_shape_L3x2e19_rhs_fp64"] = (fm.cpu().numpy(),
+                                                   dict(kind="rhs", D=D1, N=N1, kernel=k1, n=nt1m, kmax=48))
+        plan_m.close()
+        del n_m
+        log(f"[bench] Table-1 shape, L={L1m}: 100 steps in {t1m*1e3:.1f} ms")
         nt1 = synth.n0_uniform_head(N1, 3, 16)
         f = plan.rhs(torch.tensor(nt1, dtype=torch.float64, device="cuda:0"))
         checks["table1_shape_rhs_fp64"] = (f.cpu().numpy(), dict(kind="rhs", D=D1, N=N1, kernel=k1, n=nt1, kmax=48))
@@ -563,6 +581,8 @@ def main():
                               "its TT cores (ranks 1,3,3,1; 6 paths merged into 1 gain term), N=2^19, "
                               "n0 uniform on [1,16] seed 3, 100 Heun steps h=1e-3, fp64",
                   "L": int(tab1[0]), "seconds_100_steps": round(t1, 5), "rhs_per_s": round(2 * s1 / t1, 1),
+                  "mixed_radix": {"L": L1m, "seconds_100_steps": round(t1m, 5),
+                                  "rhs_per_s": round(2 * s1 / t1m, 1)},
                   "paper_seconds_100_steps": {"1 core": 257.80, "128 cores": 12.22},
                   "paper_context": "Table 1: TT path with MKL ClusterFFT on CPU cores (kernel exponents and "
                                    "initial data not stated in the paper)"}
@@ -637,6 +657,7 @@ def main():
         "plain_fp64_rhs_per_s": round(plain_rate, 2),
         "batched_rhs_per_s": {"batch": args.batch, **batched} if batched else None,
         "d5_n2e20_batch64_rhs_per_s": c5 or None,
+        "d5_n2e20_batch64_L5x2e20_rhs_per_s": c5_mixed or None,
         "d5_n2e20_sqrt_sum_kernel_rhs_per_s": c5b,
         "paper_table1_shape": table1,
         "tensor_train": tt_lines,
