@@ -528,8 +528,9 @@ def main():
         n0 = np.stack([synth.n0_uniform_head(N5, s, 16) for s in range(B)])
         c5b = {"batch": B, "rank_per_order": 32, "distinct_columns": 32,
                "fit_max_err_over_max_C": float(f"{ferr / fv.max():.3e}"), "fit_seconds": round(tfit, 2)}
-        for prec in ("fp64", "fp32c"):
-            plan = agg.Plan(D5, N5, k5, prec, batch=B)
+        for mixed, prec in ((False, "fp64"), (False, "fp32c"), (True, "fp64"), (True, "fp32c")):
+            plan = agg.Plan(D5, N5, k5, prec, batch=B, mixed=mixed)
+            L5 = int(agg.plan_tables(D5, N5, k5, prec, mixed=mixed)[0])
             n = torch.tensor(n0.reshape(-1), dtype=torch.float64, device="cuda:0")
             h, s5 = 1e-4, 3
             plan.solve(n, h, h, stats=False)      # one untimed step
@@ -541,12 +542,13 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             t5 = e0.elapsed_time(e1) / 1000.0
-            c5b[prec] = round(2 * s5 * B / t5, 2)
+            key = prec + ("_L5x2e20" if mixed else "")
+            c5b[key] = round(2 * s5 * B / t5, 2)
             f = plan.rhs(torch.tensor(n0.reshape(-1), dtype=torch.float64, device="cuda:0"))
-            checks[f"d5_n2e20_sqrt_sum_rhs_{prec}_member0"] = (
+            checks[f"d5_n2e20_sqrt_sum_rhs_{key}_member0"] = (
                 f.cpu().numpy()[:N5], dict(kind="rhs", D=D5, N=N5, kernel=k5, n=n0[0], kmax=80))
-            log(f"[bench] D=5 N=2^20 sqrt-sum kernel (rank 32, u=32) batch {B} {prec}: {s5} steps in "
-                f"{t5*1e3:.1f} ms -> {c5b[prec]} RHS/s")
+            log(f"[bench] D=5 N=2^20 sqrt-sum kernel (rank 32, u=32) batch {B} {prec} L={L5}: {s5} steps in "
+                f"{t5*1e3:.1f} ms -> {c5b[key]} RHS/s")
             plan.close()
             del n
             torch.cuda.empty_cache()
