@@ -113,8 +113,6 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
   }
   for (int d = 2; d <= D; ++d) {
     if (!byd[d]) continue;
-    for (int m = 0; m < d; ++m)
-      if (!all_finite(byd[d]->U[m], (int64_t)byd[d]->rank * N)) { *err = "non-finite kernel factor"; return AGG_ENONFINITE; }
     if (byd[d]->weight)
       for (int r = 0; r < byd[d]->rank; ++r)
         if (!std::isfinite(byd[d]->weight[r])) { *err = "non-finite kernel weight"; return AGG_ENONFINITE; }
@@ -148,8 +146,14 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
         const double* col = byd[d]->U[m] + (size_t)r * N;
         int id = -1;
         for (size_t j = 0; dedup && j < uptr.size(); ++j)
-          if (std::memcmp(uptr[j], col, sizeof(double) * (size_t)N) == 0) { id = (int)j; break; }
-        if (id < 0) { uptr.push_back(col); id = (int)uptr.size() - 1; }
+          if (uptr[j] == col || std::memcmp(uptr[j], col, sizeof(double) * (size_t)N) == 0) { id = (int)j; break; }
+        if (id < 0) {
+          // a column bitwise equal to a distinct one is finite with it: only
+          // new columns are scanned
+          if (!all_finite(col, N)) { *err = "non-finite kernel factor"; return AGG_ENONFINITE; }
+          uptr.push_back(col);
+          id = (int)uptr.size() - 1;
+        }
         P.colmap.push_back(id);
         cmap[std::make_tuple(d, m, r)] = id;
       }
