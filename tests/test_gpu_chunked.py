@@ -190,17 +190,21 @@ def sum_full():
     return dict(D=D, N=N, B=B, k=k, kw=kw, kd=dense_kernel(k), n0=n0, fit_err=fit_err, amp=amp)
 
 
-# batch 64 with term weights is the launch configuration bench.py times; the
-# other cases take 4 states (u = 64 spectra would not fit 64 states in HBM)
-@pytest.mark.parametrize("prec,weighted,B", [("fp64", False, 4), ("fp64", True, 64), ("fp32c", True, 64),
-                                             ("fp32", True, 4)])
-def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted, B):
+# batch 64 with term weights is the launch configuration bench.py times (at
+# the transform lengths 2^23 and, mixed-radix, 5 2^20); the other cases take 4
+# states (u = 64 spectra would not fit 64 states in HBM)
+@pytest.mark.parametrize("prec,weighted,B,mixed", [("fp64", False, 4, False), ("fp64", True, 64, False),
+                                                   ("fp32c", True, 64, False), ("fp32", True, 4, False),
+                                                   ("fp64", True, 64, True), ("fp32c", True, 64, True)])
+def test_chunked_sum_kernel_full_size_batch(sum_full, prec, weighted, B, mixed):
     c = sum_full
     D, N = c["D"], c["N"]
     k = c["kw"] if weighted else c["k"]
-    tab = oracle.plan_tables(D, N, {d: np.array(v["U"] if weighted else v) for d, v in k.items()}, prec)
-    say(f"[sum kernel full] D={D} N={N} B={B} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
-    plan = agg.Plan(D, N, k, prec=prec, batch=B)
+    tab = oracle.plan_tables(D, N, {d: np.array(v["U"] if weighted else v) for d, v in k.items()}, prec,
+                             mixed=mixed)
+    say(f"[sum kernel full] D={D} N={N} B={B} L={tab['L']} u={tab['u']} chunks={len(tab['chunks'])} prec={prec}")
+    assert tab["L"] == (5 << 20 if mixed else 1 << 23)
+    plan = agg.Plan(D, N, k, prec=prec, batch=B, mixed=mixed)
     n = torch.tensor(c["n0"][:B].reshape(-1), device=DEV)
     f = plan.rhs(n)
     torch.cuda.synchronize()
