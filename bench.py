@@ -385,6 +385,9 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="profiling aid: time only the primary precision (on --batch states if > 0), "
                          "no pass timing, no other lines")
+    ap.add_argument("--quick-d5", type=int, default=0, choices=[0, 1, 2],
+                    help="profiling aid: time the passes of the D=5 N=2^20 batch (additive kernel, --batch states, "
+                         "default 64) at L = 2^23 (1) or 5 2^20 (2) and exit")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="profiling aid: also copy a float64 tensor of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -404,6 +407,19 @@ def main():
 
     import paper_1905_09071_amd as agg
     import synth
+
+    if args.quick_d5:
+        # the D=5, N=2^20 batch's row and fused column passes, a few launches each
+        cc = synth.config("C5a")
+        B5 = args.batch if args.batch > 0 else cc["n0"].shape[0]
+        mixed = args.quick_d5 == 2
+        t5 = agg.plan_tables(cc["D"], cc["N"], cc["kernel"], args.prec, mixed=mixed)
+        plan = agg.Plan(cc["D"], cc["N"], cc["kernel"], args.prec, batch=B5, mixed=mixed)
+        n = torch.tensor(cc["n0"][:B5].reshape(-1), dtype=torch.float64, device="cuda:0")
+        us = {w: plan.profile_pass(n, w, reps=2) for w in (1, 3)}
+        print(json.dumps({"quick_d5": True, "prec": args.prec, "batch": B5, "L": int(t5[0]), "M1": int(t5[1]),
+                          "M2": int(t5[2]), "row_us": round(us[1], 1), "fused_col_us": round(us[3], 1)}))
+        return
 
     c = synth.config("C3")
     D, N, dt = c["D"], c["N"], c["dt"]

@@ -436,7 +436,8 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   // weighting writes them directly and the transform starts at its second stage.
   constexpr int R1 = stage_radix(M1, 1, StageRadix<T, M1>::value);   // radix of the first stage
   const int64_t rest = N - 2 * (int64_t)j2_0;
-  const bool prune = kColPrune<T, LEAN> && !CWAVE && (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
+  const bool prune = kColPrune<T, LEAN> && !CWAVE && (M1 & (M1 - 1)) == 0 &&
+                     (rest < 0 ? -1 : rest / (2 * (int64_t)M2)) < M1 / R1;
   auto put = [&](int slot, int j1, cplx<T> v) {
     if (prune) {
       if (j1 < M1 / R1) {
@@ -495,9 +496,12 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
       if (lane == 0) red[wave][c - cb] = dsum;
     }
     lds_barrier();
-    // transforms per register pass: fewer at the largest M1 to stay within 256 VGPRs
+    // transforms per register pass: fewer above 1024 values and at the
+    // mixed-radix lengths, to stay within 256 VGPRs (four groups per pass
+    // spilled to scratch memory there: at 1280 values the spill traffic more
+    // than doubled the pass's HBM writes)
     // lean launches transform one column per pass (ub = 1): one group of columns per register pass
-    constexpr int FNB = LEAN ? GMAX : GMAX * (M1 >= 2048 ? 2 : kColBatch);
+    constexpr int FNB = LEAN ? GMAX : GMAX * ((M1 > 1024 || M1 % 3 == 0 || M1 % 5 == 0) ? 2 : kColBatch);
     constexpr int RF = StageRadix<T, M1>::value;
     cplx<T>* fb = buf;   // forward transforms' result
     if constexpr (CWAVE) {
