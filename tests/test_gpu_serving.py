@@ -139,6 +139,31 @@ def test_saturating_mix_equals_alone(prec):
             assert eo <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_configured_horizon_requests(prec):
+    """Requests of the serving shape at its configured horizon, t_end in [1, 20]
+    (1000 to 1500 Heun steps of h = 1e-3, sizes and exponents for which that step
+    is inside Heun's stability interval), served together: each result against
+    the oracle's Heun trajectory."""
+    reqs = []
+    for i, (D, N, a, t_end) in enumerate(((2, 1024, 0.1, 1.0), (3, 1024, 0.25, 1.5), (3, 2048, 0.2, 1.2),
+                                          (2, 2048, 0.3, 1.0))):
+        reqs.append(dict(D=D, N=N, a=a, kernel=synth.kernel_ballistic(D, N, a),
+                         n0=synth.n0_uniform_head(N, 300 + i, 16), dt=1e-3, t_end=t_end))
+    eng = agg.Engine(0)
+    tickets = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in reqs]
+    res = drain(eng, tickets, [r["N"] for r in reqs])
+    eng.close()
+    for r, t in zip(reqs, tickets):
+        rc, out, st = res[t]
+        assert rc == agg.AGG_OK
+        assert st.steps == len(__import__("oracle").time_grid(r["dt"], r["t_end"]))
+        eo = vs_oracle(out, r)
+        say(f"[serve-horizon] D={r['D']} N={r['N']} a={r['a']} t_end={r['t_end']} steps={st.steps}: "
+            f"rel err vs oracle {eo:.3e}")
+        assert eo <= TOL[prec]
+
+
 def test_budget_and_errors():
     N = 4096
     k = synth.kernel_ballistic(3, N, 0.5)
