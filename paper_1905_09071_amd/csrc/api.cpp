@@ -383,11 +383,24 @@ struct agg_plan {
   hipGraphExec_t gexec = nullptr;
   double* g_state = nullptr;
   double g_dt = 0.0;
+  // captured whole solve of at most kSolveGraphSteps steps (the opening forward
+  // pass, every step, the last step) for one (state pointer, step, step count,
+  // last step), captured at the second consecutive call with that key; and the
+  // key of the previous call
+  hipGraphExec_t sexec = nullptr;
+  double* s_state = nullptr;
+  double s_dt = 0.0, s_last = 0.0;
+  int64_t s_steps = 0;
+  double* k_state = nullptr;
+  double k_dt = 0.0, k_last = 0.0;
+  int64_t k_steps = -1;
   double tilt = 0.0;          // binary32 plans: exponential tilt of agg_rhs's gain transforms
 };
 
 // Heun steps per captured graph of the time loop.
 constexpr int64_t kGraphSteps = 16;
+// Longest solve captured whole (4 kernel nodes per step).
+constexpr int64_t kSolveGraphSteps = 64;
 
 static void drop_graph(agg_plan* p);
 
@@ -584,10 +597,73 @@ static agg_status full_step(agg_plan* p, hipStream_t stream, double* n, double h
   return run_on(p, stream, CM_H2_FWD, h, n, nullptr, false);
 }
 
+// The last step of a solve: its second stage starts no forward pass.
+static agg_status last_step(agg_plan* p, hipStream_t stream, double* n, double h) {
+  agg_status rc;
+  if ((rc = run_on(p, stream, CM_H1, h, n, nullptr, true))) return rc;
+  if ((rc = run_on(p, stream, CM_H1, h, n, nullptr, false))) return rc;
+  if ((rc = run_on(p, stream, CM_H2, h, n, nullptr, true))) return rc;
+  return run_on(p, stream, CM_H2, h, n, nullptr, false);
+}
+
 static void drop_graph(agg_plan* p) {
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   p->gexec = nullptr;
   p->g_state = nullptr;
+  if (p->sexec) (void)hipGraphExecDestroy(p->sexec);
+  p->sexec = nullptr;
+  p->s_state = nullptr;
+}
+
+// Ends the capture begun on the plan's capture stream and instantiates it into
+// *exec (rc: the status of the captured enqueues).
+static agg_status finish_capture(agg_plan* p, agg_status rc, hipGraphExec_t* exec) {
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+  if (rc != AGG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    *exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  return AGG_OK;
+}
+
+static agg_status begin_capture(agg_plan* p) {
+  hipError_t e = hipSuccess;
+  if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  return AGG_OK;
+}
+
+// The graph of a whole solve of nsteps <= kSolveGraphSteps steps for (n, dt,
+// last_dt): the same launches as the direct path, in the same order.
+static agg_status solve_graph(agg_plan* p, double* n, double dt, int64_t nsteps, double last_dt) {
+  if (p->sexec && p->s_state == n && p->s_dt == dt && p->s_steps == nsteps && p->s_last == last_dt) return AGG_OK;
+  if (p->sexec) {   // its launches may still run
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipGraphExecDestroy(p->sexec);
+    p->sexec = nullptr;
+    p->s_state = nullptr;
+  }
+  agg_status rc = begin_capture(p);
+  if (rc) return rc;
+  rc = run_on(p, p->cap_stream, CM_FWD, 0.0, n, nullptr, false);
+  for (int64_t k = 0; k + 1 < nsteps && rc == AGG_OK; ++k) rc = full_step(p, p->cap_stream, n, dt);
+  if (rc == AGG_OK) rc = last_step(p, p->cap_stream, n, last_dt);
+  if ((rc = finish_capture(p, rc, &p->sexec))) return rc;
+  p->s_state = n;
+  p->s_dt = dt;
+  p->s_steps = nsteps;
+  p->s_last = last_dt;
+  return AGG_OK;
 }
 
 // The graph of kGraphSteps full steps for (n, h), captured on a private stream
@@ -599,27 +675,13 @@ static agg_status step_graph(agg_plan* p, double* n, double h) {
   // statistics returns before the device is done): the executable graph must
   // outlive them
   if (p->gexec) (void)hipStreamSynchronize(p->stream);
-  drop_graph(p);
-  hipError_t e = hipSuccess;
-  if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-  e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  agg_status rc = AGG_OK;
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  p->gexec = nullptr;
+  p->g_state = nullptr;
+  agg_status rc = begin_capture(p);
+  if (rc) return rc;
   for (int64_t k = 0; k < kGraphSteps && rc == AGG_OK; ++k) rc = full_step(p, p->cap_stream, n, h);
-  hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(p->cap_stream, &graph);
-  if (rc != AGG_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc;
-  }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) {
-    p->gexec = nullptr;
-    return hip_fail(e, "hipGraphInstantiate");
-  }
+  if ((rc = finish_capture(p, rc, &p->gexec))) return rc;
   p->g_state = n;
   p->g_dt = h;
   return AGG_OK;
@@ -732,6 +794,21 @@ static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, 
     }
     return AGG_OK;
   }
+  // a short solve repeating the previous call's arguments: its whole captured
+  // graph (the previous call ran every launch directly, so every kernel's
+  // one-time set-up is done)
+  const bool repeat = nsteps <= kSolveGraphSteps && p->k_state == n && p->k_dt == dt && p->k_steps == nsteps &&
+                      p->k_last == last_dt;
+  p->k_state = n;
+  p->k_dt = dt;
+  p->k_steps = nsteps;
+  p->k_last = last_dt;
+  if (repeat) {
+    if ((rc = solve_graph(p, n, dt, nsteps, last_dt))) return rc;
+    hipError_t e = hipGraphLaunch(p->sexec, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return AGG_OK;
+  }
   if ((rc = run(p, CM_FWD, 0.0, n, nullptr, false))) return rc;
   // steps 0..nsteps-2 are full steps with dt; the last one (last_dt) does not
   // start another forward pass.  Step 0 runs directly (it also sets the kernel
@@ -751,10 +828,7 @@ static agg_status heun_steps(agg_plan* p, double* n, double dt, int64_t nsteps, 
   }
   for (; s < full; ++s)
     if ((rc = full_step(p, p->stream, n, dt))) return rc;
-  if ((rc = run(p, CM_H1, last_dt, n, nullptr, true))) return rc;
-  if ((rc = run(p, CM_H1, last_dt, n, nullptr, false))) return rc;
-  if ((rc = run(p, CM_H2, last_dt, n, nullptr, true))) return rc;
-  return run(p, CM_H2, last_dt, n, nullptr, false);
+  return last_step(p, p->stream, n, last_dt);
 }
 
 agg_status agg_rk2_step(agg_plan* p, double* n, double dt) {

@@ -384,6 +384,31 @@ def test_graph_replayed_time_loop_equals_eager_steps(prec):
         assert torch.equal(a, b), f"trial {trial}"
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_repeated_short_solve_replays_its_whole_graph(prec):
+    """A short solve repeating the previous call's arguments replays one captured
+    graph of the whole solve; every replay equals the same steps launched one by
+    one, and other calls in between drop nothing."""
+    D, N, dt, steps = 4, 1000, 1e-3, 10
+    k = synth.kernel_ballistic(D, N, 0.3)
+    plan = agg.Plan(D, N, k, prec)
+    a = torch.empty(N, dtype=torch.float64, device=DEV)
+    for trial in range(3):
+        n0 = synth.n0_random_dense(N, 90 + trial, decay=0.01)
+        b = torch.tensor(n0, device=DEV)
+        for _ in range(steps):
+            plan.rk2_step(b, dt)                        # eager launches
+        outs = []
+        for rep in range(3):   # direct, then captured at the repeat, then replayed
+            a.copy_(torch.tensor(n0, device=DEV))
+            plan.solve(a, dt, steps * dt, stats=False)
+            torch.cuda.synchronize()
+            outs.append(a.clone())
+        for rep, o in enumerate(outs):
+            assert torch.equal(o, b), f"trial {trial}, call {rep}"
+    plan.close()
+
+
 def test_batched_graph_solve_equals_single_solves():
     """agg_solve of a batch replays its captured graphs over all states; each
     member equals the same solve of that state alone (both launches narrow the
