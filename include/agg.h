@@ -202,7 +202,9 @@ typedef struct {
 
 /* Integrate n from t = 0 to t_end with step dt in place by repeated Heun steps
  * (Sec. 3, as agg_rk2_step; full steps are replayed from captured HIP graphs of
- * 16 steps, which compute exactly what eager steps compute).  Time grid: the step
+ * 16 steps, and a solve of at most 64 steps that repeats the previous call's
+ * state pointer, dt and t_end from one captured graph of the whole solve; both
+ * compute exactly what eager steps compute).  Time grid: the step
  * count is round(t_end/dt) when t_end/dt is within 1e-9 (relative) of an
  * integer, else ceil(t_end/dt) with the last step shortened to reach t_end;
  * t_end = 0 takes no step.  With st == NULL the call is asynchronous.  With st
