@@ -240,10 +240,11 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   cplx<T>* buf = tw + M1;
   cplx<T>* alt = buf + (size_t)a.ub * GMAX * STR;
   __shared__ double red[NWAVE][kColBatch];
-  // launches that fill the GPU, columns of 256 and 512 values: each transform
-  // is held by one wavefront in registers (fft_wave.h), the wavefronts taking
-  // the columns of a group in turn; smaller launches keep the workgroup-wide
-  // stages, whose several wavefronts per transform give shorter chains
+  // launches that fill the GPU, columns of 256 and 512 values: each forward
+  // transform is held by one wavefront in registers (fft_wave.h), the
+  // wavefronts taking the columns of a group in turn; smaller launches keep the
+  // workgroup-wide stages, whose several wavefronts per transform give shorter
+  // chains
   constexpr bool CWAVE = LEAN && (M1 == 256 || M1 == 512);
   const int wave_u = uniform_int(threadIdx.x >> 6);
 
@@ -342,10 +343,9 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   if (inv) {
     lds_barrier();
     cplx<T>* ib = buf;   // inverse transforms' result
-    if constexpr (CWAVE) {
-      for (int q = wave_u; q < g; q += NWAVE) fft_wave_lds<T, M1, +1, StageRadix<T, M1>::value>(buf + (size_t)q * STR, tw);
-      lds_barrier();
-    } else if constexpr (!kColPingPong<T, M1, LEAN>) {
+    // (the g inverse transforms keep the workgroup-wide stages in every
+    // variant: one wavefront per transform would leave most of them idle)
+    if constexpr (!kColPingPong<T, M1, LEAN>) {
       fft_batch<T, M1, +1, GMAX, STR, NT, StageRadix<T, M1>::value>(buf, g, tw);
     } else {
       ib = fft_batch_pp<T, M1, +1, GMAX, STR, NT, StageRadix<T, M1>::value>(buf, alt, g, tw);
