@@ -283,11 +283,25 @@ agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, 
 
 // Partial dot products are kept for M2 column groups per column: room for any
 // launch-time column group g' <= g (the plan API narrows g for small batches).
-size_t slot_bytes(const PlanTables& T) {
-  size_t cs = complex_bytes(T.prec);
-  size_t ngroups = T.M2;
-  return (size_t)T.u * T.M * cs + (size_t)T.M * cs + (size_t)T.u * ngroups * 8 + (size_t)T.u * 8 +
-         2 * (size_t)colorder_len(T.N, T.M2) * 8;
+// A launch with fewer column groups than CUs takes narrower groups, so that
+// every CU holds one (each column is still transformed whole).
+static int spread_g(const PlanTables& T, int nslots) {
+  int g = T.g;
+  while (g > 1 && (int64_t)nslots * (T.M2 / g) < kSpreadWorkgroups) g >>= 1;
+  return g;
+}
+
+// Shares per column group: a launch that still has fewer groups than CUs at
+// g = 1 splits each group's distinct columns over several workgroups (at least
+// kSplitMinColumns columns each; each share repeats the group's inverse
+// transform, one transform against the share's forward ones).
+static int col_split(const PlanTables& T, int nslots, int g) {
+  const int64_t items = (int64_t)nslots * (T.M2 / g);
+  if (items >= kSpreadWorkgroups) return 1;
+  const int64_t want = (kSpreadWorkgroups + items - 1) / items;
+  const int64_t most = T.u / kSplitMinColumns;
+  const int64_t s = std::min(want, most);
+  return s > 1 ? (int)s : 1;
 }
 
 // Buffers of `batch` slots sharing one kernel set, each kind carved from one
@@ -303,6 +317,8 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   s.dots = (int64_t)((size_t)T.u * ngroups * 8);
   s.G = (int64_t)((size_t)std::max(T.u, 1) * 8);
   s.k1 = s.ntil = (int64_t)((size_t)colorder_len(T.N, T.M2) * 8);   // column order
+  // stage 1's state, kept for stage 2 when the plan's launches split their column groups
+  s.nprev = col_split(T, batch, spread_g(T, batch)) > 1 ? s.k1 : 0;
   std::memset(sd, 0, sizeof(*sd));
   if ((rc = arena.alloc((size_t)s.Z1 * batch, &sd->Z1))) return rc;
   if ((rc = arena.alloc((size_t)s.V * batch, &sd->V))) return rc;
@@ -310,6 +326,7 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   if ((rc = arena.alloc((size_t)s.G * batch, (void**)&sd->G))) return rc;
   if ((rc = arena.alloc((size_t)s.k1 * batch, (void**)&sd->k1))) return rc;
   if ((rc = arena.alloc((size_t)s.ntil * batch, (void**)&sd->ntil))) return rc;
+  if (s.nprev && (rc = arena.alloc((size_t)s.nprev * batch, (void**)&sd->nprev))) return rc;
   sd->cols = st.cols;
   sd->tab = st.tabs; sd->coef = st.coef; sd->ntab = st.ntab;
   sd->o_pids = st.o_pids; sd->o_qoff = st.o_qoff; sd->o_qids = st.o_qids; sd->o_qkm = st.o_qkm; sd->o_pfrom = st.o_pfrom;
@@ -319,10 +336,6 @@ agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena&
   sd->mode = CM_NONE; sd->row_on = 0; sd->dt = 0.0;
   if (stride) *stride = s;
   return AGG_OK;
-}
-
-agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd) {
-  return build_slots(T, st, arena, 1, sd, nullptr);
 }
 
 agg_status row_lds_check(const PlanTables& T, int ntab, int ncoef) {
@@ -342,10 +355,10 @@ LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc
   a.mode = -1;
   a.twP1 = st.twP1; a.twP2 = st.twP2; a.twLlo = st.twLlo; a.twLhi = st.twLhi;
   a.M1 = T.M1; a.M2 = T.M2; a.g = T.g; a.b = T.b; a.L = T.L;
-  // a launch with fewer column groups than CUs takes narrower groups, so that
-  // every CU holds one (each column is still transformed whole)
-  if (spread)
-    while (a.g > 1 && (int64_t)nslots * (T.M2 / a.g) < kSpreadWorkgroups) a.g >>= 1;
+  if (spread) {
+    a.g = spread_g(T, nslots);
+    a.usplit = col_split(T, nslots, a.g);
+  }
   a.umax = std::max(T.u, 1);
   a.cmax = T.cmax;
   a.ub = col_batch(T.prec, T.M1, T.u, nslots * (T.M2 / a.g));
@@ -570,6 +583,8 @@ agg_status agg_plan_destroy(agg_plan* p) {
 static agg_status run_on(agg_plan* p, hipStream_t stream, int mode, double dt, double* state, double* outp,
                          bool row, double tilt = 0.0) {
   LaunchArgs a = base_args(p->tab, p->st, nullptr, p->batch, true);
+  if (a.usplit > 1 && (mode == CM_H1 || mode == CM_H2 || mode == CM_H2_FWD) && !p->base.nprev)
+    return set_error(AGG_EINVAL, "split column pass without the stage-1 state buffer");
   a.base = p->base;
   a.stride = p->stride;
   a.mode = mode;

@@ -50,15 +50,15 @@ agg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 agg_status build_slots(const PlanTables& T, const SharedTables& st, DeviceArena& arena, int batch,
                        SlotDesc* sd, SlotStride* stride);
 agg_status build_shared(const PlanTables& T, hipStream_t s, DeviceArena& arena, SharedTables* st);
-agg_status build_slot(const PlanTables& T, const SharedTables& st, DeviceArena& arena, SlotDesc* sd);
-size_t slot_bytes(const PlanTables& T);
 // Dynamic LDS a row-pass workgroup may take, and the check that a kernel set's
 // row pass fits (AGG_EUNSUPPORTED otherwise).
 constexpr size_t kRowLdsLimit = 160 * 1024 - 4096;
 agg_status row_lds_check(const PlanTables& T, int ntab, int ncoef);
 // spread: narrow the column group g below the plan's when the launch has fewer
-// column groups than CUs; every launch that shares a slot's partial dot
-// products must be built with the same choice and slot count.
+// column groups than CUs, and split the groups' distinct columns over several
+// workgroups when that is still too few; every launch that shares a slot's
+// partial dot products or Heun vectors must be built with the same choice and
+// slot count (a split stage-2 launch reads the state its stage-1 launch kept).
 LaunchArgs base_args(const PlanTables& T, const SharedTables& st, const SlotDesc* d_slots, int nslots,
                      bool spread = false);
 

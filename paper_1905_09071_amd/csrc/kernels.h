@@ -38,6 +38,8 @@ struct SlotDesc {
   double* n_state;        // state (used when the launch passes no external state)
   double* k1;             // Heun stage-1 slope, N
   double* ntil;           // Heun stage-1 state n~, N
+  double* nprev;          // the state at Heun stage 1 (column order): read by stage 2 of
+                          //   launches whose column groups are split (LaunchArgs::usplit)
   const double* cols;     // u distinct factor columns, N each (binary64)
   void* Z1;               // u*M stored complex values
   void* V;                // M stored complex values
@@ -79,7 +81,7 @@ struct SlotDesc {
 // Byte strides between consecutive slots' buffers when every slot of a launch
 // shares one kernel set and its buffers are carved from batched allocations.
 struct SlotStride {
-  int64_t k1, ntil, Z1, V, dots, G;
+  int64_t k1, ntil, Z1, V, dots, G, nprev;
 };
 
 struct LaunchArgs {
@@ -104,6 +106,8 @@ struct LaunchArgs {
   int tab_max;            // largest term-table int blob among the slots
   int coef_max;           // largest coefficient blob (Tp + Tq) among the slots
   int lean;               // column pass variant for launches that fill the GPU
+  int usplit;             // column pass: workgroups sharing one column group's distinct
+                          //   columns (1: one workgroup per group)
   double tilt;            // binary32 spectra: inputs weighted by exp(tilt s), gain by exp(-tilt s) (0: off)
   // serving launches (captured once, replayed every tick): logical slot s of
   // the launch is table entry active[1 + s] while s < active[0] (its workgroups
@@ -120,6 +124,7 @@ constexpr int kLeanWorkgroups = 512;     // column-pass workgroups from which a 
 constexpr int kLeanMaxM1 = 512;          // largest column length with a lean column-pass variant
 constexpr int kRowRegCols = 4;          // row pass: distinct columns up to which unpacked spectra stay in registers
 constexpr int kSpreadWorkgroups = 256;   // column-pass workgroups a small launch is spread over (one per CU)
+constexpr int kSplitMinColumns = 4;      // fewest distinct columns a share of a split column group takes
 constexpr int kTTMaxRank = 8;            // largest tensor-train rank (the chain's per-bin vectors live in registers)
 
 }  // namespace agg

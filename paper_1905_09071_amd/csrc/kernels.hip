@@ -150,6 +150,7 @@ __device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
   sd.V = (void*)((char*)sd.V + slot * a.stride.V);
   sd.dots = (double*)((char*)sd.dots + slot * a.stride.dots);
   sd.G = (double*)((char*)sd.G + slot * a.stride.G);
+  sd.nprev = (double*)((char*)sd.nprev + slot * a.stride.nprev);
   return sd;
 }
 
@@ -200,7 +201,13 @@ __device__ __forceinline__ void load_table(cplx<T>* dst, const void* src) {
 }
 
 // ---------------------------------------------------------------------------
-// Column pass.  Work item = (slot, group of g adjacent columns j2).
+// Column pass.  Work item = (slot, group of g adjacent columns j2, share).
+// With usplit > 1 shares (launches with fewer groups than CUs) each share
+// transforms its own range of the distinct factor columns; every share
+// computes the group's inverse and epilogue, which its weighting needs, and
+// share 0 alone stores them.  A state that Heun stage 2 overwrites in place
+// would then be read by shares that start after share 0 has written it, so
+// split launches keep stage 1's state in nprev and stage 2 reads it from there.
 // LDS: the M1 twiddles, then up to ub*g columns of M1 values.
 // Every global value the pass needs (the combined spectrum's columns, the
 // state and Heun vectors, the first kColPrefetch factor columns and the
@@ -250,9 +257,14 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
 
   const int M2 = a.M2, g = a.g, lgg = a.lgg;
   const int ngroups = M2 >> lgg;
-  const int w = xcd_contiguous(blockIdx.x, a.nslots * ngroups);
-  const int lslot = w / ngroups;
-  const int grp = w - lslot * ngroups;
+  const int nshare = a.usplit > 1 ? a.usplit : 1;
+  // the shares of a group are adjacent work items (one XCD, whose L2 serves
+  // their common loads)
+  const int w = xcd_contiguous(blockIdx.x, a.nslots * ngroups * nshare);
+  const int wg = w / nshare;
+  const int share = w - wg * nshare;
+  const int lslot = wg / ngroups;
+  const int grp = wg - lslot * ngroups;
   const int slot = launch_slot(a, lslot);
   if (slot < 0) return;
   const SlotDesc sd = slot_desc(a, slot);
@@ -260,6 +272,9 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   double dt;
   slot_stage(a, sd, mode, row_on_unused, dt);
   if (mode == CM_NONE) return;
+  if (share > 0 && !mode_has_forward(mode)) return;   // nothing of its own to transform
+  const bool split = nshare > 1;
+  const bool store = share == 0;                     // the epilogue's stores
   const int64_t N = sd.N;
   const int64_t M = (int64_t)M1 * M2;
   const int j2_0 = grp * g;
@@ -267,6 +282,8 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
   const int lane = tid & 63, wave = tid >> 6;
   const int nitems = g * M1;
   const int u = sd.u;
+  // this share's distinct columns [c_lo, c_hi)
+  const int c_lo = (int)(((int64_t)share * u) / nshare), c_hi = (int)(((int64_t)(share + 1) * u) / nshare);
   const bool inv = mode_has_inverse(mode), fwd = mode_has_forward(mode);
   const bool stage2 = (mode == CM_H2 || mode == CM_H2_FWD);
   double* state = a.ext_state ? a.ext_state + (size_t)slot * N : sd.n_state;
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
       int64_t s = pos[it] + e, ci = cix[it] + e;
       bool ok = s >= 1 && s <= N;
       pe[it][e] = ok ? (stage2 ? ldg(sd.ntil + ci) : ldg(state + (s - 1))) : 0.0;
-      pn[it][e] = (!LEAN && ok && stage2) ? ldg(state + (s - 1)) : 0.0;
+      pn[it][e] = (!LEAN && ok && stage2) ? (split ? ldg(sd.nprev + ci) : ldg(state + (s - 1))) : 0.0;
       pk[it][e] = (!LEAN && ok && stage2) ? ldg(sd.k1 + ci) : 0.0;
 #pragma unroll
       for (int q = 0; q < UP; ++q) uc[q][it][e] = (ok && q < u) ? ldg(sd.cols + ((size_t)q * CSZ + ci)) : 0.0;
@@ -402,14 +419,18 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
             } else if (mode == CM_RHS_ACC) {
               stg(out + (s - 1), ldg(out + (s - 1)) + f);
             } else if (mode == CM_H1) {
-              stg(sd.k1 + (cix[it] + e), f);
               val = pe[it][e] + dt * f;
-              stg(sd.ntil + (cix[it] + e), val);
+              if (store) {
+                stg(sd.k1 + (cix[it] + e), f);
+                stg(sd.ntil + (cix[it] + e), val);
+                if (split) stg(sd.nprev + (cix[it] + e), pe[it][e]);
+              }
             } else {
-              const double nb = LEAN ? ldg(state + (s - 1)) : pn[it][e];
+              const double nb =
+                  LEAN ? (split ? ldg(sd.nprev + (cix[it] + e)) : ldg(state + (s - 1))) : pn[it][e];
               const double kb = LEAN ? ldg(sd.k1 + (cix[it] + e)) : pk[it][e];
               val = nb + 0.5 * dt * (kb + f);
-              stg(state + (s - 1), val);
+              if (store) stg(state + (s - 1), val);
             }
           }
           if (e == 0) s0[it] = val; else s1[it] = val;
@@ -455,8 +476,8 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
     }
     return x;
   };
-  for (int cb = 0; cb < u; cb += a.ub) {
-    const int nc = u - cb < a.ub ? u - cb : a.ub;
+  for (int cb = c_lo; cb < c_hi; cb += a.ub) {
+    const int nc = c_hi - cb < a.ub ? c_hi - cb : a.ub;
     // weighted columns x_c = U_c * state for c in [cb, cb+nc)
 #pragma unroll
     for (int q = 0; q < UP; ++q) {
@@ -1301,7 +1322,7 @@ template <class T, int M1>
 static hipError_t launch_col_t(const LaunchArgs& a, hipStream_t s) {
   constexpr int GMAX = (1024 / M1) > 0 ? 1024 / M1 : 1;
   const size_t tbuf = (size_t)a.ub * GMAX * lds_len(M1);   // transform buffer
-  dim3 grid(a.nslots * (a.M2 / a.g));
+  dim3 grid(a.nslots * (a.M2 / a.g) * (a.usplit > 1 ? a.usplit : 1));
   // from M1 = 1024 the register cap of the lean variant (two workgroups per CU)
   // spills the per-item state to scratch; those launches keep every register
   if constexpr (M1 <= kLeanMaxM1) {

@@ -189,6 +189,44 @@ def test_tt_chain_across_chunks(prec):
     assert e <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_split_column_pass_is_exact(prec):
+    """A launch with fewer column groups than CUs splits each group's 114
+    distinct core columns over several workgroups (N = 4096: 16 groups of one
+    column at one state, 16 shares); a batch of 16 states fills the CUs with
+    unsplit groups of the same width.  Each batch member's RHS, and its state
+    after a 5-step solve (stage 2 reading stage 1's kept state), equals the
+    single-state plan's result bit for bit; member 0 also against the oracle."""
+    rng = np.random.default_rng(84)
+    D, N, B = 4, 4096, 16
+    tt = {2: _cores(rng, N, [1, 3, 1]), 3: _cores(rng, N, [1, 4, 4, 1]), 4: _cores(rng, N, [1, 6, 6, 6, 1])}
+    ref_tables = oracle.plan_tables_tt(D, N, tt, prec)
+    assert ref_tables["M2"] == 16 and ref_tables["u"] == 114
+    states = np.stack([synth.n0_random_dense(N, 85 + b, decay=2e-3) for b in range(B)])
+    h = 1e-5
+    batch = agg.Plan(D, N, prec=prec, tt=tt, batch=B)
+    nb = torch.tensor(states.ravel(), device=DEV)
+    fb = batch.rhs(nb).cpu().numpy().reshape(B, N)
+    batch.solve(nb, h, 5 * h, stats=False)
+    sb = nb.cpu().numpy().reshape(B, N)
+    batch.close()
+    one = agg.Plan(D, N, prec=prec, tt=tt)
+    for b in (0, 7, 15):
+        n1 = torch.tensor(states[b], device=DEV)
+        f1 = one.rhs(n1).cpu().numpy()
+        one.solve(n1, h, 5 * h, stats=False)
+        s1 = n1.cpu().numpy()
+        say(f"[split column pass] {prec} member {b}: rhs equal {np.array_equal(f1, fb[b])}, "
+            f"solve equal {np.array_equal(s1, sb[b])}")
+        assert np.array_equal(f1, fb[b]) and np.array_equal(s1, sb[b])
+        if b == 0:
+            cp = {d: oracle.tt_paths(c) for d, c in tt.items()}
+            e = rel(f1, oracle.total_rhs(*oracle.rhs_fft(D, N, cp, states[0])))
+            say(f"  rhs err vs oracle {e:.3e}")
+            assert e <= TOL[prec]
+    one.close()
+
+
 def test_tt_chain_refusals():
     rng = np.random.default_rng(5)
     N = 64
