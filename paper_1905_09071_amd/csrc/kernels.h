@@ -118,6 +118,7 @@ struct LaunchArgs {
 
 constexpr int kColBatch = 4;             // upper bound of LaunchArgs::ub
 constexpr int kColThreads = 512;         // threads of a column-pass workgroup
+constexpr int kChunkThreads = 512;       // threads of a chunked row-pass workgroup (one per CU: its LDS)
 constexpr int kColPrefetch = 4;          // factor columns held in registers by the column pass
 constexpr int kColLdsBudget = 120 * 1024; // LDS the column pass may use
 constexpr int kLeanWorkgroups = 512;     // column-pass workgroups from which a launch counts as saturating

@@ -139,6 +139,20 @@ template <class T> __device__ __forceinline__ cplx<T> lane_swap1(cplx<T> v) {
   return r;
 }
 
+// The value held by lane `src` of this wavefront, word by word (ds_bpermute: a
+// lane-crossing move, no LDS allocation).  The source lane must be active.
+template <class T> __device__ __forceinline__ cplx<T> lane_read(cplx<T> v, int src) {
+  static_assert(sizeof(cplx<T>) % 4 == 0, "whole 32-bit words");
+  constexpr int W = sizeof(cplx<T>) / 4;
+  int w[W];
+  __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_ds_bpermute(src << 2, w[i]);
+  cplx<T> r;
+  __builtin_memcpy(&r, w, sizeof(r));
+  return r;
+}
+
 // Descriptor of one slot: from device memory, or built from the launch's base
 // descriptor and strides (no dependent load before the first data request).
 __device__ __forceinline__ SlotDesc slot_desc(const LaunchArgs& a, int slot) {
@@ -383,8 +397,12 @@ __global__ __launch_bounds__(kColThreads, LEAN ? 4 : 1) void col_kernel(LaunchAr
         }
       }
     }
+    // (columns with a zero weight add exact zeros to the finite sums: skipped;
+    // a tensor-train kernel weights only its last cores' columns)
+    const auto Gu = uniform_ptr((const double*)sd.G);
     for (int c = UP; c < u; ++c) {
-      const double Gc = ldg(sd.G + c);
+      const double Gc = Gu[c];
+      if (Gc == 0.0) continue;
       const double* col = sd.cols + (size_t)c * CSZ;
 #pragma unroll
       for (int it = 0; it < IPT; ++it)
@@ -915,10 +933,10 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
 // per-wave partial dots and the u dot products.
 // ---------------------------------------------------------------------------
 template <class T, int M2>
-__global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_kernel(LaunchArgs a) {
-  constexpr int NT = RowThreads<M2, false>::value;
+__global__ __launch_bounds__(kChunkThreads, 1) void row_chunk_kernel(LaunchArgs a) {
+  constexpr int NT = kChunkThreads;
   constexpr bool TW_LDS = M2 <= 512;
-  constexpr int NB = (M2 >= 1024 && NT > kThreads) ? 4096 / M2 : ((2048 / M2) > 0 ? 2048 / M2 : 1);
+  constexpr int NB = (4096 / M2) > 0 ? 4096 / M2 : 1;   // a butterfly per thread at radix 8
   constexpr int STR = lds_len(M2);
   constexpr int NWAVE = NT / 64;
   constexpr int UPT = (M2 + NT - 1) / NT;       // combine units (bin pairs) per thread
@@ -996,6 +1014,21 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
   const bool tt = TTK && sd.tt > 0;
   const auto ttrec = uniform_ptr(sd.tab + sd.o_tt);
   const auto ttid = uniform_ptr(sd.tab);
+  // rows of at most 256 values (fewer bin pairs than threads): the chain of a
+  // bin pair is shared by TOS adjacent lanes of one wavefront, lane og of the
+  // pair holding outputs og, og + TOS, ... of every core's product and reading
+  // the product's inputs from the pair's other lanes; each output sums the
+  // same products in the same order as a single thread would
+  constexpr int TOS = !TTK ? 1 : (NT / M2 >= kTTMaxRank ? kTTMaxRank : (NT / M2 > 1 ? NT / M2 : 1));
+  constexpr bool TSPLIT = TOS > 1;
+  constexpr int TOJ = kTTMaxRank / TOS;             // outputs per lane
+  const int tu = wave * (64 / TOS) + lane / TOS;    // this lane's bin pair
+  const int tog = lane % TOS, tbase = lane - tog;   // its outputs, the pair's first lane
+  const bool ton = TSPLIT && tt && tu < nunits;
+  cplx<T> sA[TOJ], sB[TOJ], YAs = czero<T>(), YBs = czero<T>();
+#pragma unroll
+  for (int j = 0; j < TOJ; ++j) sA[j] = sB[j] = czero<T>();
+  const cplx<T> wks = ton ? twL<T>(a, k1 + (int64_t)M1 * tu) : czero<T>();
   for (int h = 0; h < nch; ++h) {
     const int c0 = chunked ? chc[h] : 0;
     const int nc = chunked ? chc[h + 1] - c0 : uniform_int(u);
@@ -1013,6 +1046,88 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
     }
     lds_barrier();
     fft_batch<T, M2, -1, NB, STR, NT, StageRadix<T, M2>::value>(X, nc * nrows, tw);
+    if constexpr (TSPLIT) {
+      if (tt) {
+        int iB = 0, rB = 0;
+        if (ton) pair_of(tu, iB, rB);
+        const int iA = tu;
+        const bool zero_bin = (k1 == 0 && iA == 0);
+        const bool self = (rB == 0 && iB == iA);
+        if (ton) {   // the pair's columns unpacked by its lanes in turn
+          for (int c = tog; c < nc; c += TOS) {
+            const cplx<T> ZA = X[(c * nrows) * STR + lds_pad(iA)];
+            const cplx<T> ZB = X[(c * nrows + rB) * STR + lds_pad(iB)];
+            cplx<T> xa, xb;
+            if (zero_bin) {
+              xa = cplx<T>{ZA.re + ZA.im, Real<T>::zero()};
+              xb = cplx<T>{ZA.re - ZA.im, Real<T>::zero()};
+            } else {
+              const cplx<T> zc = cconj(ZB);
+              const cplx<T> E = cplx<T>{half_of(ZA.re + zc.re), half_of(ZA.im + zc.im)};
+              const cplx<T> dd = csub(ZA, zc);
+              const cplx<T> t = cmul(wks, cplx<T>{half_of(dd.im), half_of(-dd.re)});
+              xa = cadd(E, t);
+              xb = self ? xa : cconj(csub(E, t));
+            }
+            X[(c * nrows) * STR + lds_pad(iA)] = cnorm(xa);
+            if (zero_bin) nyq[c] = cnorm(xb);
+            else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
+          }
+        }
+        wave_lds_sync();   // a pair's lanes sit in one wavefront
+        if (ton) {
+          auto xat = [&](int c, bool b) -> cplx<T> {
+            if (c < 0) return czero<T>();
+            if (!b) return X[(c * nrows) * STR + lds_pad(iA)];
+            return zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)];
+          };
+          for (int k = t0; k < t1; ++k) {
+            const int term = ttrec[7 * k], lam = ttrec[7 * k + 1], d = ttrec[7 * k + 2];
+            const int rin = ttrec[7 * k + 3], rout = ttrec[7 * k + 4], lo = ttrec[7 * k + 5];
+            cplx<T> inA[kTTMaxRank], inB[kTTMaxRank];   // the pair's vector, from its lanes
+            if (lam > 1) {
+#pragma unroll
+              for (int a2 = 0; a2 < kTTMaxRank; ++a2) {
+                if (a2 < rin) {
+                  inA[a2] = lane_read(sA[a2 / TOS], tbase + a2 % TOS);
+                  inB[a2] = lane_read(sB[a2 / TOS], tbase + a2 % TOS);
+                }
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < TOJ; ++j) {
+              const int b = tog + j * TOS;
+              cplx<T> nA = czero<T>(), nB = czero<T>();
+              if (b < rout) {
+                if (lam == 1) {
+                  nA = xat(ttid[lo + b], false);
+                  nB = xat(ttid[lo + b], true);
+                } else {
+#pragma unroll
+                  for (int a2 = 0; a2 < kTTMaxRank; ++a2) {
+                    if (a2 < rin) {
+                      const int c = ttid[lo + a2 * rout + b];
+                      if (c >= 0) {
+                        nA = cadd(nA, cmul(inA[a2], xat(c, false)));
+                        nB = cadd(nB, cmul(inB[a2], xat(c, true)));
+                      }
+                    }
+                  }
+                }
+              }
+              sA[j] = cnorm(nA);
+              sB[j] = cnorm(nB);
+            }
+            if (lam == d && tog == 0) {
+              const T cf = Real<T>::from_d(pcoef[2 * term]);
+              YAs = cnorm(cadd(YAs, cscale(sA[0], cf)));
+              YBs = cnorm(cadd(YBs, cscale(sB[0], cf)));
+            }
+          }
+        }
+        continue;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
       const int unit = tid + i * NT;
@@ -1043,7 +1158,7 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
         if (zero_bin) nyq[c] = cnorm(xb);
         else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
       }
-      if constexpr (TTK) {
+      if constexpr (TTK && !TSPLIT) {
         if (tt) {
           // cores [t0, t1) of this chunk: v <- v * (the core's matrix of
           // spectra at this bin); the first core of a term starts v, the last
@@ -1112,20 +1227,25 @@ __global__ __launch_bounds__((RowThreads<M2, false>::value), 1) void row_chunk_k
     }
   }
   lds_barrier();   // every chunk's reads of X are done: rows 0-1 take the packed sum
-#pragma unroll
-  for (int i = 0; i < UPT; ++i) {
-    const int unit = tid + i * NT;
-    if (unit >= nunits) continue;
+  auto pack = [&](int unit, cplx<T> A, cplx<T> B, cplx<T> w) {
     int iB, rB;
     pair_of(unit, iB, rB);
     const int iA = unit;
-    const cplx<T> A = YA[i], B = YB[i];
     if (k1 == 0 && iA == 0) {
       X[0] = cnorm(cplx<T>{A.re + B.re, A.re - B.re});
     } else {
       const cplx<T> s = cadd(A, cconj(B)), df = csub(A, cconj(B));
-      X[lds_pad(iA)] = cnorm(cadd(s, cmul_i(cmulc(df, wk[i]))));
-      if (!(rB == 0 && iB == iA)) X[rB * STR + lds_pad(iB)] = cnorm(cadd(cconj(s), cmul_i(cmul(wk[i], cconj(df)))));
+      X[lds_pad(iA)] = cnorm(cadd(s, cmul_i(cmulc(df, w))));
+      if (!(rB == 0 && iB == iA)) X[rB * STR + lds_pad(iB)] = cnorm(cadd(cconj(s), cmul_i(cmul(w, cconj(df)))));
+    }
+  };
+  if (TSPLIT && tt) {
+    if (ton && tog == 0) pack(tu, YAs, YBs, wks);
+  } else {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int unit = tid + i * NT;
+      if (unit < nunits) pack(unit, YA[i], YB[i], wk[i]);
     }
   }
   lds_barrier();
@@ -1408,8 +1528,7 @@ static hipError_t launch_row_t(const LaunchArgs& a, hipStream_t s) {
       chunk_attr = true;
     }
     if (smem > 160 * 1024 - 4096) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((row_chunk_kernel<T, M2>), dim3(a.nslots * (a.M1 / 2 + 1)),
-                       dim3(RowThreads<M2, false>::value), smem, s, a);
+    hipLaunchKernelGGL((row_chunk_kernel<T, M2>), dim3(a.nslots * (a.M1 / 2 + 1)), dim3(kChunkThreads), smem, s, a);
     return hipGetLastError();
   }
   constexpr bool kHasLean = M2 <= 512;
