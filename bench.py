@@ -393,6 +393,8 @@ def main():
     ap.add_argument("--quick-d5", type=int, default=0, choices=[0, 1, 2],
                     help="profiling aid: time the passes of the D=5 N=2^20 batch (additive kernel, --batch states, "
                          "default 64) at L = 2^23 (1) or 5 2^20 (2) and exit")
+    ap.add_argument("--quick-tt", action="store_true",
+                    help="profiling aid: run only the tensor-train lines and print their JSON")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="profiling aid: also copy a float64 tensor of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -424,6 +426,11 @@ def main():
         us = {w: plan.profile_pass(n, w, reps=2) for w in (1, 3)}
         print(json.dumps({"quick_d5": True, "prec": args.prec, "batch": B5, "L": int(t5[0]), "M1": int(t5[1]),
                           "M2": int(t5[2]), "row_us": round(us[1], 1), "fused_col_us": round(us[3], 1)}))
+        return
+
+    if args.quick_tt:
+        tt_out = tensor_train_lines(agg, synth, torch, np, {}, log)
+        print(json.dumps({"quick_tt": True, "tensor_train": tt_out}))
         return
 
     c = synth.config("C3")
