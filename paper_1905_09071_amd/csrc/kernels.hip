@@ -603,6 +603,10 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
   constexpr bool WAVE = M2 == 256 || (M2 == 512 && !(LEAN && std::is_same<T, ff>::value));   // (that one spilled)
   constexpr int E = WAVE ? M2 / 64 : 1;         // values per lane of a wavefront transform
   constexpr int VPT = WAVE ? E : (2 * M2 + NT - 1) / NT;   // output values per thread
+  // lanes sharing a bin pair's gain terms (rows of at most 64 values, where both
+  // variants run 256 threads, so every variant shares a pair the same way)
+  constexpr int TS = M2 <= 64 ? (256 / M2 >= 8 ? 8 : 256 / M2) : 1;
+  static_assert(TS == 1 || NT / TS >= (M2 > 32 ? M2 : 32), "a lane group per bin pair");
   extern __shared__ __align__(16) unsigned char smem[];
 
   const int M1 = a.M1;
@@ -824,6 +828,70 @@ __global__ __launch_bounds__((RowThreads<M2, LEAN>::value), LEAN ? 4 : 1) void r
           X[lds_pad(iA)] = cnorm(pack_a(YA, YB, wk));
         } else if (!self) {
           X[rB * STR + lds_pad(iB)] = cnorm(pack_b(YA, YB, wk));
+        }
+      }
+    }
+  } else if (TS > 1 && u > kRowRegCols && Tpu >= 2 * TS) {
+    // rows of at most 64 values with many gain terms (fewer bin pairs than
+    // threads): a bin pair's terms are shared by TS adjacent lanes of one
+    // wavefront in contiguous blocks; a block that starts inside a running
+    // product recomputes its prefix with the same operations in the same order,
+    // and the lanes' sums are added in lane order.  (Every launch variant takes
+    // this path for such a slot: with more than kRowRegCols columns none keeps
+    // the spectra in registers.)
+    const int su = wave * (64 / TS) + lane / TS;   // this lane's bin pair
+    const int sg = lane % TS, sbase = lane - sg;
+    const bool on = su < nunits;
+    int iB = 0, rB = 0;
+    if (on) pair_of(su, iB, rB);
+    const int iA = su;
+    const bool zero_bin = (k1 == 0 && iA == 0);
+    const bool self = (rB == 0 && iB == iA);
+    cplx<T> wk = czero<T>();
+    if (on) {
+      const int64_t e = k1 + (int64_t)M1 * su;
+      wk = cmul(ldg((const cplx<T>*)a.twLhi + (e >> a.b)), ldg((const cplx<T>*)a.twLlo + (e & lmask)));
+      for (int c = sg; c < u; c += TS) {   // the pair's columns unpacked by its lanes in turn
+        cplx<T> xa, xb;
+        unpack(c, iA, iB, rB, zero_bin, self, wk, xa, xb);
+        X[(c * nrows) * STR + lds_pad(iA)] = cnorm(xa);
+        if (zero_bin) nyq[c] = cnorm(xb);
+        else if (!self) X[(c * nrows + rB) * STR + lds_pad(iB)] = cnorm(xb);
+      }
+    }
+    wave_lds_sync();   // a pair's lanes sit in one wavefront
+    if (on) {
+      cplx<T> YA = czero<T>(), YB = czero<T>(), PA = czero<T>(), PB = czero<T>();
+      const int per = (Tpu + TS - 1) / TS;
+      const int t0 = min(Tpu, sg * per), t1 = min(Tpu, t0 + per);
+      for (int t = t0; t < t1; ++t) {
+        const int oe = poff[t + 1];
+        int o = t == t0 ? poff[t] : pfrom[t];
+        bool fresh = o == poff[t];
+        for (; o < oe; ++o) {
+          int c = pids[o];
+          const cplx<T> fa = X[(c * nrows) * STR + lds_pad(iA)];
+          const cplx<T> fb = zero_bin ? nyq[c] : X[(c * nrows + rB) * STR + lds_pad(iB)];
+          PA = fresh ? fa : cmul(PA, fa);
+          PB = fresh ? fb : cmul(PB, fb);
+          fresh = false;
+        }
+        const T cf = Real<T>::from_d(pcoef[t]);
+        YA = cadd(YA, cscale(PA, cf));
+        YB = cadd(YB, cscale(PB, cf));
+      }
+      cplx<T> SA = lane_read(YA, sbase), SB = lane_read(YB, sbase);
+#pragma unroll
+      for (int j = 1; j < TS; ++j) {
+        SA = cadd(SA, lane_read(YA, sbase + j));
+        SB = cadd(SB, lane_read(YB, sbase + j));
+      }
+      if (sg == 0) {
+        if (zero_bin) {
+          X[0] = cnorm(cplx<T>{SA.re + SB.re, SA.re - SB.re});
+        } else {
+          X[lds_pad(iA)] = cnorm(pack_a(SA, SB, wk));
+          if (!self) X[rB * STR + lds_pad(iB)] = cnorm(pack_b(SA, SB, wk));
         }
       }
     }

@@ -227,6 +227,37 @@ def test_split_column_pass_is_exact(prec):
     one.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_many_term_combine_shared_by_lanes(prec):
+    """The ranks-6 kernel written as its 235 rank paths (114 distinct columns)
+    at N = 4096, rows of 16 values: each bin pair's gain terms are shared by 8
+    lanes of a wavefront.  One state (the full row-pass variant) and two states
+    (the lean variant) give bit for bit the same RHS and Heun step, which agree
+    with the oracle."""
+    rng = np.random.default_rng(80)
+    D, N = 4, 4096
+    tt = {2: _cores(rng, N, [1, 3, 1]), 3: _cores(rng, N, [1, 4, 4, 1]), 4: _cores(rng, N, [1, 6, 6, 6, 1])}
+    paths = {d: agg.tt_expand(N, c) for d, c in tt.items()}
+    assert agg.plan_tables(D, N, paths, prec)[2] == 16
+    n = synth.n0_random_dense(N, 86, decay=2e-3)
+    h = 1e-5
+    out = {}
+    for B in (1, 2):
+        plan = agg.Plan(D, N, paths, prec, batch=B)
+        nt = torch.tensor(np.tile(n, B), device=DEV)
+        f = plan.rhs(nt).cpu().numpy().reshape(B, N)
+        plan.rk2_step(nt, h)
+        out[B] = (f, nt.cpu().numpy().reshape(B, N))
+        plan.close()
+    assert np.array_equal(out[1][0][0], out[2][0][1]) and np.array_equal(out[1][1][0], out[2][1][1])
+    cp = {d: oracle.tt_paths(c) for d, c in tt.items()}
+    rhs = lambda v: oracle.total_rhs(*oracle.rhs_fft(D, N, cp, v))
+    e1 = rel(out[1][0][0], rhs(n))
+    e2 = rel(out[1][1][0], oracle.heun_solve(rhs, n, h, h))
+    say(f"[many-term combine] {prec}: rhs err {e1:.3e}, heun err {e2:.3e}")
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+
+
 def test_tt_chain_refusals():
     rng = np.random.default_rng(5)
     N = 64
