@@ -202,6 +202,36 @@ def test_fifo_admission_under_tight_budget():
     assert admits == sorted(admits)
 
 
+def test_submits_from_several_threads():
+    """Requests submitted concurrently from 4 client threads (each submitter
+    plans and stages its own request) all finish with distinct tickets, and each
+    result equals bit for bit the same request submitted from one thread into
+    another engine; one sample agrees with the oracle's trajectory."""
+    from concurrent.futures import ThreadPoolExecutor
+    reqs = synth.serving_requests(24, seed=14, t_end_range=(0.003, 0.02), log2n_range=(10, 13))
+    sub = lambda eng, r: eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], "fp64")
+    eng = agg.Engine(0)
+    with ThreadPoolExecutor(4) as pool:
+        tickets = list(pool.map(lambda r: sub(eng, r), reqs))
+    assert len(set(tickets)) == len(reqs)
+    res = drain(eng, tickets, [r["N"] for r in reqs])
+    c = eng.counters()
+    eng.close()
+    assert c["completed"] == len(reqs) and c["running"] == 0 and c["queued"] == 0
+    eng1 = agg.Engine(0)
+    t1 = [sub(eng1, r) for r in reqs]
+    res1 = drain(eng1, t1, [r["N"] for r in reqs])
+    eng1.close()
+    for r, t, u in zip(reqs, tickets, t1):
+        assert res[t][0] == agg.AGG_OK and res1[u][0] == agg.AGG_OK
+        assert np.array_equal(res[t][1], res1[u][1])
+    i = min(range(len(reqs)), key=lambda j: reqs[j]["N"] * (1 << reqs[j]["D"]))
+    e = vs_oracle(res[tickets[i]][1], reqs[i])
+    say(f"[serve threads] {len(reqs)} requests from 4 threads; sample D={reqs[i]['D']} N={reqs[i]['N']} "
+        f"rel err vs oracle {e:.3e}")
+    assert e <= TOL["fp64"]
+
+
 def test_nonfinite_request_is_isolated():
     """A request stepped far outside Heun's stability interval blows up; it ends
     AGG_ENONFINITE (state still returned) while the requests that share its
