@@ -189,19 +189,23 @@ def test_tt_chain_across_chunks(prec):
     assert e <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 def test_split_column_pass_is_exact(prec):
     """A launch with fewer column groups than CUs splits each group's 114
     distinct core columns over several workgroups (N = 4096: 16 groups of one
-    column at one state, 16 shares); a batch of 16 states fills the CUs with
-    unsplit groups of the same width.  Each batch member's RHS, and its state
-    after a 5-step solve (stage 2 reading stage 1's kept state), equals the
-    single-state plan's result bit for bit; member 0 also against the oracle."""
+    column at one state, 16 shares; binary32 spectra, half the bytes per row,
+    give rows of 32 values: 32 groups, 8 shares); a batch of 16 states (8 in
+    binary32) fills the CUs with unsplit groups of the same width (a larger
+    batch would widen the groups, which regroups the binary64 partial dot
+    products).  Each batch member's RHS, and its state after a 5-step solve
+    (stage 2 reading stage 1's kept state), equals the single-state plan's
+    result bit for bit; member 0 also against the oracle."""
     rng = np.random.default_rng(84)
-    D, N, B = 4, 4096, 16
+    D, N = 4, 4096
+    B = 8 if prec == "fp32" else 16
     tt = {2: _cores(rng, N, [1, 3, 1]), 3: _cores(rng, N, [1, 4, 4, 1]), 4: _cores(rng, N, [1, 6, 6, 6, 1])}
     ref_tables = oracle.plan_tables_tt(D, N, tt, prec)
-    assert ref_tables["M2"] == 16 and ref_tables["u"] == 114
+    assert ref_tables["M2"] == (32 if prec == "fp32" else 16) and ref_tables["u"] == 114
     states = np.stack([synth.n0_random_dense(N, 85 + b, decay=2e-3) for b in range(B)])
     h = 1e-5
     batch = agg.Plan(D, N, prec=prec, tt=tt, batch=B)
@@ -211,7 +215,7 @@ def test_split_column_pass_is_exact(prec):
     sb = nb.cpu().numpy().reshape(B, N)
     batch.close()
     one = agg.Plan(D, N, prec=prec, tt=tt)
-    for b in (0, 7, 15):
+    for b in (0, B // 2 - 1, B - 1):
         n1 = torch.tensor(states[b], device=DEV)
         f1 = one.rhs(n1).cpu().numpy()
         one.solve(n1, h, 5 * h, stats=False)
