@@ -349,25 +349,29 @@ def tensor_train_lines(agg, synth, torch, np, checks, log):
     cross = {d: agg.tt_cross(d, N, ballistic, tol=1e-12, rmax=8, seed=d) for d in (2, 3)}
     tcross = time.perf_counter() - t0
     ttb = {d: c for d, (c, _) in cross.items()}
-    rates = {}
-    for prec in ("fp64", "fp32c"):
-        plan = agg.Plan(3, N, prec=prec, tt=ttb)
-        n = torch.tensor(n0, dtype=torch.float64, device="cuda:0")
-        t, _ = time_steps(plan, n, h, steps, 2, torch)
-        rates[prec] = round(2 * steps / t, 1)
-        f = plan.rhs(torch.tensor(n0, dtype=torch.float64, device="cuda:0"))
-        checks[f"tt_cross_ballistic_rhs_{prec}"] = (f.cpu().numpy(), dict(kind="rhs", D=3, N=N, tt=ttb,
-                                                                          n=n0, kmax=48))
-        plan.close()
-        del n
-        log(f"[bench] TT-cross ballistic D=3 N={N} {prec}: {rates[prec]} RHS/s")
+    rates, rates_mixed = {}, {}
+    Lm = int(agg.plan_tables_tt(3, N, ttb, "fp64", mixed=True)[0])
+    for mixed in (False, True):
+        for prec in ("fp64", "fp32c"):
+            plan = agg.Plan(3, N, prec=prec, tt=ttb, mixed=mixed)
+            n = torch.tensor(n0, dtype=torch.float64, device="cuda:0")
+            t, _ = time_steps(plan, n, h, steps, 2, torch)
+            (rates_mixed if mixed else rates)[prec] = round(2 * steps / t, 1)
+            f = plan.rhs(torch.tensor(n0, dtype=torch.float64, device="cuda:0"))
+            key = f"tt_cross_ballistic{'_L3x2e16' if mixed else ''}_rhs_{prec}"
+            checks[key] = (f.cpu().numpy(), dict(kind="rhs", D=3, N=N, tt=ttb, n=n0, kmax=48))
+            plan.close()
+            del n
+            log(f"[bench] TT-cross ballistic D=3 N={N} {prec}{f' L={Lm}' if mixed else ''}: "
+                f"{(rates_mixed if mixed else rates)[prec]} RHS/s")
     out["tt_cross_ballistic"] = {
         "workload": "D=3 N=65536, kernel (sum_m i_m^(1/3))^2 (sum_m 1/i_m)^(1/2) at orders 2 and 3, "
                     "compressed on the host by agg_tt_cross (rmax 8), n0 uniform on [1,16], 20 Heun steps h=1e-6",
         "ranks": {d: [1] + [int(x.shape[2]) for x in c] for d, (c, _) in cross.items()},
         "cross_err_est": {d: float(f"{e:.3e}") for d, (_, e) in cross.items()},
         "cross_seconds": round(tcross, 2),
-        "rhs_per_s": rates}
+        "rhs_per_s": rates,
+        "mixed_radix": {"L": Lm, "rhs_per_s": rates_mixed}}
     return out
 
 

@@ -61,7 +61,8 @@ enum {
  * accumulating f, with separate forward, row, inverse and Heun launches per
  * stage: the unshared, unfused reference evaluation.
  * AGG_MIXED_RADIX may be OR-ed into the precision of agg_plan_create,
- * agg_plan_tables and agg_submit: the transform length may then be 3 2^a or
+ * agg_plan_create_tt, agg_plan_tables, agg_plan_tables_tt and agg_submit: the
+ * transform length may then be 3 2^a or
  * 5 2^a (radix-3 or radix-5 first stage in the column transforms) when that is
  * shorter than the power of two, e.g. 5 2^20 instead of 2^23 for D = 5,
  * N = 2^20 (37.5% fewer spectral bytes): the smallest 3 2^a or 5 2^a (a >= 4)
@@ -132,7 +133,8 @@ typedef struct {
  * the loss weights of order d come from the product of the first d-1 cores'
  * matrices of dot products U_c . n (times 1/(d-1)!), applied to core d's
  * columns.  Same state layout, calls (agg_rhs, agg_rk2_step, agg_solve,
- * agg_rhs_noalloc) and precisions as a CP plan; no AGG_PLAIN option.
+ * agg_rhs_noalloc), precisions and AGG_MIXED_RADIX option as a CP plan; no
+ * AGG_PLAIN option.
  * Errors: as agg_plan_create, and AGG_EINVAL for ranks outside [1, 8] or
  * r_0, r_d != 1; AGG_EUNSUPPORTED when the transform's rows exceed 512 values
  * (N D above 2^20) or one core has more distinct columns than a row-pass chunk

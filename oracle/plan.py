@@ -196,7 +196,7 @@ def plan_tables(D: int, N: int, kernel: dict, prec: str = "fp64", dedup: bool = 
                 pterms=pterms, qterms=qterms, chunks=chunks, flat=np.array(flat, dtype=np.int64))
 
 
-def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64"):
+def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64", mixed: bool = False):
     """The written rules for kernels in tensor-train form (Sec. 2): {d: cores},
     core m of shape (r_{m-1}, N, r_m).
 
@@ -204,7 +204,8 @@ def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64"):
     T2  Column ids: scan d ascending, cores m = 1..d, a < r_{m-1}, b < r_m; the
         core column H^(m)[a, :, b] gets -1 when all its values are zero, else the
         id of the first earlier bitwise-equal column, else the next new id.
-    T3  Split and tile as P6/P7 with u distinct columns.  Unsupported when M2 > 512.
+    T3  Split and tile as P6/P7 with u distinct columns (with the mixed-radix
+        option: X2/X6/X7 first, as for CP kernels).  Unsupported when M2 > 512.
     T4  Chunks always (the chain runs in the chunked row pass): capacity as in
         P8, cores taken in scan order, a chunk taking the next core while the
         union of distinct non-negative ids stays within the capacity, else a
@@ -243,17 +244,33 @@ def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64"):
             cores_rec.append((t, m, rin, rout, ids))
     u = len(seen)
     cs = PREC_BYTES[prec]
-    lg = _log2_exact(M)
-    M1 = 1 << ((lg + 1) // 2)
-    M2 = M // M1
-    while u * 2 * M2 * cs > 65536 and M1 < 2048:
-        M1 *= 2
-        M2 //= 2
-    if M1 > 2048 or M2 < 2:
-        raise Unsupported(f"no two-pass split for L={L} with u={u}")
+    split = None
+    if mixed:
+        Lm = None
+        for base in (48, 80):
+            c = base
+            while c < De * N - 1:
+                c *= 2
+            if Lm is None or c < Lm:
+                Lm = c
+        if Lm < L:
+            split = _mixed_split(Lm, u, cs)
+            if split is not None:
+                L, M = Lm, Lm // 2
+    if split is not None:
+        M1, M2, g = split
+    else:
+        lg = _log2_exact(M)
+        M1 = 1 << ((lg + 1) // 2)
+        M2 = M // M1
+        while u * 2 * M2 * cs > 65536 and M1 < 2048:
+            M1 *= 2
+            M2 //= 2
+        if M1 > 2048 or M2 < 2:
+            raise Unsupported(f"no two-pass split for L={L} with u={u}")
+        g = min(M2, max(1, 1024 // M1))
     if M2 > 512:
         raise Unsupported("tensor-train chains need rows of at most 512 values")
-    g = min(M2, max(1, 1024 // M1))
     cmax = 151552 // (2 * (M2 + M2 // 16) * cs)
     chunks = []
     cols, cores = set(), []

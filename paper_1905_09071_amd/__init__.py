@@ -80,13 +80,14 @@ def make_tt_terms(D: int, N: int, tt: dict):
     return arr, len(items), keep
 
 
-def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64") -> np.ndarray:
+def plan_tables_tt(D: int, N: int, tt: dict, prec: str = "fp64", mixed: bool = False) -> np.ndarray:
     """The planner's integer tables of a tensor-train kernel set (host only)."""
     terms, nt, keep = make_tt_terms(D, N, tt)
+    code = PREC[prec] | (AGG_MIXED_RADIX if mixed else 0)
     ln = ctypes.c_int64(0)
-    lib().agg_plan_tables_tt(D, N, terms, nt, PREC[prec], None, 0, ctypes.byref(ln))
+    lib().agg_plan_tables_tt(D, N, terms, nt, code, None, 0, ctypes.byref(ln))
     out = np.zeros(max(ln.value, 1), dtype=np.int64)
-    check(lib().agg_plan_tables_tt(D, N, terms, nt, PREC[prec],
+    check(lib().agg_plan_tables_tt(D, N, terms, nt, code,
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.size, ctypes.byref(ln)))
     del keep
     return out[:ln.value]
@@ -205,16 +206,16 @@ class Plan:
         """plain=True: the term-by-term, unshared, unfused reference evaluation.
         tt={d: cores}: the kernel set in tensor-train form instead of CP factors
         (agg_plan_create_tt).  mixed=True: transform lengths 3 2^a and 5 2^a
-        allowed (AGG_MIXED_RADIX)."""
+        allowed (AGG_MIXED_RADIX), for CP and tensor-train kernel sets."""
         self.D, self.N, self.batch, self.prec, self.plain = D, N, batch, prec, plain
         self._stream = stream
         h = ctypes.c_void_p()
         if tt is not None:
-            if kernel is not None or plain or mixed:
-                raise ValueError("a tensor-train plan takes no CP kernel and no plain or mixed option")
+            if kernel is not None or plain:
+                raise ValueError("a tensor-train plan takes no CP kernel and no plain option")
             terms, nt, keep = make_tt_terms(D, N, tt)
-            check(lib().agg_plan_create_tt(D, N, terms, nt, PREC[prec], batch, _stream_handle(stream),
-                                           ctypes.byref(h)))
+            check(lib().agg_plan_create_tt(D, N, terms, nt, _plan_code(prec, False, mixed), batch,
+                                           _stream_handle(stream), ctypes.byref(h)))
         else:
             terms, nt, keep = make_terms(D, N, kernel)
             code = _plan_code(prec, plain, mixed)

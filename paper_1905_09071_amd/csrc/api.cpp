@@ -489,19 +489,20 @@ agg_status agg_plan_create_tt(int32_t D, int64_t N, const agg_tt_term* terms, in
   if (!out) return set_error(AGG_EINVAL, "out is NULL");
   *out = nullptr;
   if (batch < 1) return set_error(AGG_EINVAL, "batch must be >= 1");
-  if ((prec & ~0xff) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
+  if ((prec & ~(0xff | AGG_MIXED_RADIX)) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
   agg_plan* p = new agg_plan();
   std::string err;
-  agg_status rc = plan_build_tt(D, N, terms, nterms, prec, &p->tab, &err);
+  agg_status rc = plan_build_tt(D, N, terms, nterms, prec & 0xff, &p->tab, &err, (prec & AGG_MIXED_RADIX) != 0);
   if (rc != AGG_OK) { delete p; return set_error(rc, err); }
   return plan_create_from(p, batch, hip_stream, out);
 }
 
 agg_status agg_plan_tables_tt(int32_t D, int64_t N, const agg_tt_term* terms, int32_t nterms, int32_t prec,
                               int64_t* out, int64_t cap, int64_t* len) {
+  if ((prec & ~(0xff | AGG_MIXED_RADIX)) != 0) return set_error(AGG_EINVAL, "unknown plan option bits");
   PlanTables T;
   std::string err;
-  agg_status rc = plan_build_tt(D, N, terms, nterms, prec, &T, &err);
+  agg_status rc = plan_build_tt(D, N, terms, nterms, prec & 0xff, &T, &err, (prec & AGG_MIXED_RADIX) != 0);
   if (rc != AGG_OK) return set_error(rc, err);
   if (len) *len = (int64_t)T.flat.size();
   if (!out || cap < (int64_t)T.flat.size()) return set_error(AGG_EINVAL, "output capacity too small");

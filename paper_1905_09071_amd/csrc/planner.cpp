@@ -269,7 +269,7 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
 }
 
 agg_status plan_build_tt(int D, int64_t N, const agg_tt_term* terms, int nterms, int prec, PlanTables* out,
-                         std::string* err) {
+                         std::string* err, bool mixed) {
   if (D < 2 || D > AGG_MAX_D) { *err = "D must lie in [2, AGG_MAX_D]"; return AGG_EINVAL; }
   if (N < 1) { *err = "N must be >= 1"; return AGG_EINVAL; }
   if (prec != AGG_FP64 && prec != AGG_FP32 && prec != AGG_FP32C) { *err = "unknown precision"; return AGG_EINVAL; }
@@ -306,7 +306,18 @@ agg_status plan_build_tt(int D, int64_t N, const agg_tt_term* terms, int nterms,
   P.D = D; P.N = N; P.prec = prec; P.De = De;
   int64_t L = 1;
   while (L < De * N - 1) L *= 2;
-  P.L = std::max<int64_t>(L, 16); P.M = P.L / 2;
+  L = std::max<int64_t>(L, 16);
+  P.L = L; P.M = L / 2;
+  // mixed radix as for CP kernels: the smallest 3 2^a or 5 2^a (a >= 4) at
+  // least De N - 1 when it is shorter than the power of two
+  int odd = 1;
+  int64_t Lmix = L;
+  if (mixed)
+    for (int o : {3, 5}) {
+      int64_t c = 16 * o;
+      while (c < De * N - 1) c *= 2;
+      if (c < Lmix) { Lmix = c; odd = o; }
+    }
 
   // columns: every core column, deduplicated bitwise; all-zero ones get -1
   std::vector<const double*> uptr;
@@ -338,8 +349,16 @@ agg_status plan_build_tt(int D, int64_t N, const agg_tt_term* terms, int nterms,
   P.ucols.resize(P.u);
   for (int c = 0; c < P.u; ++c) P.ucols[c].assign(uptr[c], uptr[c] + N);
 
-  agg_status rc = split_pass(P, err);
-  if (rc != AGG_OK) return rc;
+  bool split_done = false;
+  if (odd > 1) {
+    P.L = Lmix; P.M = Lmix / 2;
+    split_done = split_mixed(P, odd);
+    if (!split_done) { P.L = L; P.M = L / 2; }
+  }
+  if (!split_done) {
+    agg_status rc = split_pass(P, err);
+    if (rc != AGG_OK) return rc;
+  }
   if (P.M2 > 512) { *err = "tensor-train chains need rows of at most 512 values (N D <= 2^20)"; return AGG_EUNSUPPORTED; }
 
   // chunks: whole cores in scan order

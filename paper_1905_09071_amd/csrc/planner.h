@@ -62,11 +62,12 @@ agg_status plan_build(int D, int64_t N, const agg_term* terms, int nterms, int p
 // r_lambda (the core column H^(lambda)_{a,:,b}), all-zero columns getting -1;
 // row-pass chunks group whole cores in scan order, a chunk taking the next
 // core while the union of distinct ids stays within the chunk capacity.
-// Unsupported: ranks above kTTMaxRank, rows longer than 512 values (the
-// chain's per-bin vectors are held in registers), a core with more distinct
-// columns than a chunk holds.
+// The transform length and its split follow plan_build, with the same
+// mixed-radix option.  Unsupported: ranks above kTTMaxRank, rows longer than
+// 512 values (the chain's per-bin vectors are held in registers), a core with
+// more distinct columns than a chunk holds.
 agg_status plan_build_tt(int D, int64_t N, const agg_tt_term* terms, int nterms, int prec, PlanTables* out,
-                         std::string* err);
+                         std::string* err, bool mixed = false);
 
 // exp(-2 pi i e / P) for e = 0..P-1, interleaved (re, im), binary64; and one entry.
 void twiddle_table(int64_t P, double* out);

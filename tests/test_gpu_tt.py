@@ -262,6 +262,36 @@ def test_many_term_combine_shared_by_lanes(prec):
     assert e1 <= TOL[prec] and e2 <= TOL[prec]
 
 
+@pytest.mark.parametrize("N,prec", [(4096, "fp64"), (4096, "fp32c"), (4096, "fp32"),
+                                    (65536, "fp64"), (65536, "fp32c")])
+def test_tt_chain_mixed_radix(N, prec):
+    """Random dense D = 3 cores (ranks (1,3,1), (1,4,4,1); 30 distinct columns)
+    with the mixed-radix option: L = 3 2^12 (columns of 96 values) at N = 4096
+    and L = 3 2^16 (columns of 1536 values, rows of 64) at N = 65536, instead of
+    2^14 and 2^18.  RHS and one Heun step against the oracle's CP-FFT
+    evaluation of the rank paths."""
+    rng = np.random.default_rng(87)
+    D = 3
+    tt = {2: _cores(rng, N, [1, 3, 1]), 3: _cores(rng, N, [1, 4, 4, 1])}
+    t = oracle.plan_tables_tt(D, N, tt, prec, mixed=True)
+    assert t["L"] == 3 * N and t["M1"] == {4096: 96, 65536: 1536}[N]
+    assert agg.plan_tables_tt(D, N, tt, prec, mixed=True).tolist() == t["flat"].tolist()
+    n = synth.n0_random_dense(N, 88, decay=2e-3 if N == 4096 else 1e-4)
+    h = 1e-5
+    plan = agg.Plan(D, N, prec=prec, tt=tt, mixed=True)
+    nt = torch.tensor(n, device=DEV)
+    f = plan.rhs(nt).cpu().numpy()
+    plan.rk2_step(nt, h)
+    after = nt.cpu().numpy()
+    plan.close()
+    cp = {d: oracle.tt_paths(c) for d, c in tt.items()}
+    rhs = lambda v: oracle.total_rhs(*oracle.rhs_fft(D, N, cp, v))
+    e1 = rel(f, rhs(n))
+    e2 = rel(after, oracle.heun_solve(rhs, n, h, h))
+    say(f"[tt chain mixed] N={N} L={t['L']} M1={t['M1']} M2={t['M2']} {prec}: rhs err {e1:.3e}, heun err {e2:.3e}")
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+
+
 def test_tt_chain_refusals():
     rng = np.random.default_rng(5)
     N = 64

@@ -168,8 +168,24 @@ def test_tt_tables_hand_derived():
     assert got.tolist() == want
 
 
+def test_tt_tables_mixed_radix_hand_derived():
+    """D=3, N=65536, one order-3 term with ranks (1,1,1,1) and 3 distinct
+    columns.  Power of two: L = 2^18, M = 2^17 -> M1 = 512, M2 = 256, g = 2.
+    Mixed radix: X2 gives L' = 3 2^16 = 196608 (5 2^16 = 327680 is longer),
+    M = 98304; X6: M2 = 256 (256^2 <= 98304 < 512^2), M1 = 384, no widening
+    (3*2*256*16 = 24576 <= 64 KiB), 2^9 divides L'; X7: g = 2 (1024 // 384 = 2).
+    Chunk capacity at M2 = 256: 151552 // (2*272*16) = 17, one chunk."""
+    N = 65536
+    cols = [np.full(N, v) for v in (1.0, 2.0, 3.0)]
+    cores = [c.reshape(1, N, 1) for c in cols]
+    tail = [1, 3, 3, 3, 0, 1, 1, 1, 0, 0, 2, 1, 1, 1, 0, 3, 1, 1, 2, 1, 3, 3, 0, 1, 2, 0, 1, 2]
+    assert agg.plan_tables_tt(3, N, {3: cores}).tolist() == [262144, 512, 256, 2, 3] + tail
+    assert agg.plan_tables_tt(3, N, {3: cores}, mixed=True).tolist() == [196608, 384, 256, 2, 3] + tail
+
+
+@pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("case", range(6))
-def test_tt_tables_match_the_twin(case):
+def test_tt_tables_match_the_twin(case, mixed):
     import oracle
     rng = np.random.default_rng(100 + case)
     D = [2, 3, 4, 4, 3, 4][case]
@@ -186,6 +202,6 @@ def test_tt_tables_match_the_twin(case):
         if d > 2 and 2 in tt:
             cores[-1][0, :, 0] = tt[2][1][0, :, 0]        # shared with another order
         tt[d] = cores
-    got = agg.plan_tables_tt(D, N, tt, prec)
-    want = oracle.plan_tables_tt(D, N, tt, prec)["flat"]
+    got = agg.plan_tables_tt(D, N, tt, prec, mixed=mixed)
+    want = oracle.plan_tables_tt(D, N, tt, prec, mixed=mixed)["flat"]
     assert got.tolist() == want.tolist()
