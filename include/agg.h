@@ -374,6 +374,16 @@ agg_status agg_submit(agg_engine* e, int32_t D, int64_t N, const agg_term* terms
                       int32_t nterms, const double* n0, double dt, double t_end,
                       int32_t prec, uint64_t* ticket);
 
+/* agg_submit for a kernel set in tensor-train form (the cores as
+ * agg_plan_create_tt takes them; Sec. 2, the O(N D R^2 log N) evaluation of
+ * Sec. 1): the same queue, admission, time grid, results and errors, plus the
+ * errors of agg_plan_create_tt.  The cores may be reused on return.  A request
+ * runs in the bucket of its launch geometry (its chunked row pass) beside CP
+ * requests of other geometries. */
+agg_status agg_submit_tt(agg_engine* e, int32_t D, int64_t N, const agg_tt_term* terms,
+                         int32_t nterms, const double* n0, double dt, double t_end,
+                         int32_t prec, uint64_t* ticket);
+
 /* Non-blocking.  AGG_PENDING until done; then writes n_out (host, N doubles)
  * and st (nullable), forgets the ticket, and returns the solve's status
  * (AGG_OK, AGG_ENONFINITE, ...).  AGG_ENOTFOUND for an unknown ticket. */

@@ -292,14 +292,23 @@ class Engine:
         except Exception:
             pass
 
-    def submit(self, D, N, kernel, n0, dt, t_end, prec="fp32c", mixed: bool = False) -> int:
-        terms, nt, keep = make_terms(D, N, kernel)
+    def submit(self, D, N, kernel, n0, dt, t_end, prec="fp32c", mixed: bool = False, tt: dict = None) -> int:
+        """Queue one solve (agg_submit; agg_submit_tt with tt={d: cores} instead
+        of a CP kernel)."""
+        if (kernel is None) == (tt is None):
+            raise ValueError("give either a CP kernel or tensor-train cores")
         n0 = np.ascontiguousarray(n0, dtype=np.float64)
         if n0.size != N:
             raise ValueError("n0 must have N entries")
         t = ctypes.c_uint64(0)
-        check(lib().agg_submit(self._h, D, N, terms, nt, n0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                               float(dt), float(t_end), _plan_code(prec, False, mixed), ctypes.byref(t)))
+        np0 = n0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        code = _plan_code(prec, False, mixed)
+        if tt is not None:
+            terms, nt, keep = make_tt_terms(D, N, tt)
+            check(lib().agg_submit_tt(self._h, D, N, terms, nt, np0, float(dt), float(t_end), code, ctypes.byref(t)))
+        else:
+            terms, nt, keep = make_terms(D, N, kernel)
+            check(lib().agg_submit(self._h, D, N, terms, nt, np0, float(dt), float(t_end), code, ctypes.byref(t)))
         del keep
         return t.value
 

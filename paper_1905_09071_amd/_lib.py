@@ -85,6 +85,9 @@ EXPORTS = [
     ("agg_submit", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_term),
                                     ctypes.c_int32, DP, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_uint64)]),
+    ("agg_submit_tt", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(agg_tt_term),
+                                       ctypes.c_int32, DP, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_uint64)]),
     ("agg_poll", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, DP, ctypes.POINTER(agg_request_stats)]),
     ("agg_engine_counters", ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4),
     ("agg_last_error", ctypes.c_char_p, []),

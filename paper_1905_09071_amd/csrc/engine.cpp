@@ -790,16 +790,10 @@ agg_status agg_engine_destroy(agg_engine* E) {
   return AGG_OK;
 }
 
-agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
-                      const double* n0, double dt, double t_end, int32_t prec, uint64_t* ticket) {
-  if (!E || !n0 || !ticket) return set_error(AGG_EINVAL, "NULL argument");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AGG_EINVAL, "dt must be finite and > 0");
-  if (!(t_end >= 0.0) || !std::isfinite(t_end)) return set_error(AGG_EINVAL, "t_end must be finite and >= 0");
-  auto r = std::make_unique<Request>();
-  std::string err;
-  if ((prec & ~(0xff | AGG_MIXED_RADIX)) != 0) return set_error(AGG_EINVAL, "unknown precision option bits");
-  agg_status rc = plan_build(D, N, terms, nterms, prec & 0xff, &r->tab, &err, true, (prec & AGG_MIXED_RADIX) != 0);
-  if (rc != AGG_OK) return set_error(rc, err);
+// The part of a submission after its plan is built (either kernel form).
+static agg_status submit_planned(agg_engine* E, std::unique_ptr<Request> r, int64_t N, const double* n0, double dt,
+                                 double t_end, uint64_t* ticket) {
+  agg_status rc;
   if (r->tab.u == 0) return set_error(AGG_EINVAL, "the engine needs at least one term with rank > 0");
   for (int64_t i = 0; i < N; ++i)
     if (!std::isfinite(n0[i])) return set_error(AGG_ENONFINITE, "non-finite initial value");
@@ -852,6 +846,37 @@ agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms
   rr->ready.store(true, std::memory_order_release);
   g.cv.notify_all();
   return AGG_OK;
+}
+
+static agg_status submit_checks(agg_engine* E, const double* n0, double dt, double t_end, int32_t prec,
+                                uint64_t* ticket) {
+  if (!E || !n0 || !ticket) return set_error(AGG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AGG_EINVAL, "dt must be finite and > 0");
+  if (!(t_end >= 0.0) || !std::isfinite(t_end)) return set_error(AGG_EINVAL, "t_end must be finite and >= 0");
+  if ((prec & ~(0xff | AGG_MIXED_RADIX)) != 0) return set_error(AGG_EINVAL, "unknown precision option bits");
+  return AGG_OK;
+}
+
+agg_status agg_submit(agg_engine* E, int32_t D, int64_t N, const agg_term* terms, int32_t nterms,
+                      const double* n0, double dt, double t_end, int32_t prec, uint64_t* ticket) {
+  agg_status rc = submit_checks(E, n0, dt, t_end, prec, ticket);
+  if (rc != AGG_OK) return rc;
+  auto r = std::make_unique<Request>();
+  std::string err;
+  rc = plan_build(D, N, terms, nterms, prec & 0xff, &r->tab, &err, true, (prec & AGG_MIXED_RADIX) != 0);
+  if (rc != AGG_OK) return set_error(rc, err);
+  return submit_planned(E, std::move(r), N, n0, dt, t_end, ticket);
+}
+
+agg_status agg_submit_tt(agg_engine* E, int32_t D, int64_t N, const agg_tt_term* terms, int32_t nterms,
+                         const double* n0, double dt, double t_end, int32_t prec, uint64_t* ticket) {
+  agg_status rc = submit_checks(E, n0, dt, t_end, prec, ticket);
+  if (rc != AGG_OK) return rc;
+  auto r = std::make_unique<Request>();
+  std::string err;
+  rc = plan_build_tt(D, N, terms, nterms, prec & 0xff, &r->tab, &err, (prec & AGG_MIXED_RADIX) != 0);
+  if (rc != AGG_OK) return set_error(rc, err);
+  return submit_planned(E, std::move(r), N, n0, dt, t_end, ticket);
 }
 
 agg_status agg_poll(agg_engine* E, uint64_t ticket, double* n_out, agg_request_stats* st) {

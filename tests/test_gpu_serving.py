@@ -232,6 +232,41 @@ def test_submits_from_several_threads():
     assert e <= TOL["fp64"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_tensor_train_requests_in_the_mix(prec):
+    """Requests whose kernels are given in tensor-train form (agg_submit_tt:
+    random dense D = 3 cores of ranks (1,3,1), (1,4,4,1), 30 core columns, at
+    N = 1024 and 4096; the chunked row pass's per-bin chains) served among CP
+    requests: each tensor-train result equals the same request served alone bit
+    for bit and agrees with the oracle's Heun trajectory of its rank paths."""
+    rng = np.random.default_rng(91)
+    cores = lambda N, ranks: [rng.uniform(0.1, 1.0, size=(ranks[m], N, ranks[m + 1])) for m in range(len(ranks) - 1)]
+    tts = [dict(D=3, N=N, tt={2: cores(N, [1, 3, 1]), 3: cores(N, [1, 4, 4, 1])},
+                n0=synth.n0_random_dense(N, 92 + N, decay=2e-3), dt=1e-3, t_end=0.02) for N in (1024, 4096)]
+    cps = synth.serving_requests(4, seed=93, t_end_range=(0.003, 0.01), log2n_range=(10, 12))
+    sub_tt = lambda eng, r: eng.submit(r["D"], r["N"], None, r["n0"], r["dt"], r["t_end"], prec, tt=r["tt"])
+    eng = agg.Engine(0)
+    t_tt = [sub_tt(eng, r) for r in tts]
+    t_cp = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in cps]
+    res = drain(eng, t_tt + t_cp, [r["N"] for r in tts] + [r["N"] for r in cps])
+    eng.close()
+    assert all(res[t][0] == agg.AGG_OK for t in t_cp)
+    for r, t in zip(tts, t_tt):
+        rc, out, st = res[t]
+        assert rc == agg.AGG_OK and st.steps == 20
+        e1 = agg.Engine(0)
+        u = sub_tt(e1, r)
+        rc1, out1, _ = drain(e1, [u], [r["N"]])[u]
+        e1.close()
+        assert rc1 == agg.AGG_OK and np.array_equal(out, out1)
+        cp = {d: oracle.tt_paths(c) for d, c in r["tt"].items()}
+        rhs = lambda v: oracle.total_rhs(*oracle.rhs_fft(r["D"], r["N"], cp, v))
+        ref = oracle.heun_solve(rhs, r["n0"], r["dt"], r["t_end"])
+        e = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+        say(f"[serve tt] D=3 N={r['N']} {prec}: rel err vs oracle {e:.3e}")
+        assert e <= TOL[prec]
+
+
 def test_nonfinite_request_is_isolated():
     """A request stepped far outside Heun's stability interval blows up; it ends
     AGG_ENONFINITE (state still returned) while the requests that share its
