@@ -5,6 +5,7 @@ the request (per-rank FFT evaluation of the Sec. 1 sums, Heun stepping of
 Sec. 3) and with agg_solve of the request within the parity tolerance
 (agg_solve may narrow the column group of a small launch, which regroups the
 binary64 partial dot products); admission, rejection and ticket handling."""
+import ctypes
 import sys
 import time
 
@@ -246,6 +247,18 @@ def test_tensor_train_requests_in_the_mix(prec):
     cps = synth.serving_requests(4, seed=93, t_end_range=(0.003, 0.01), log2n_range=(10, 12))
     sub_tt = lambda eng, r: eng.submit(r["D"], r["N"], None, r["n0"], r["dt"], r["t_end"], prec, tt=r["tt"])
     eng = agg.Engine(0)
+    bad = dict(tts[0], tt={2: cores(1024, [1, 9, 1])})            # a rank above 8
+    with pytest.raises(agg.AggError) as ex:
+        sub_tt(eng, bad)
+    assert ex.value.status == agg.AGG_EINVAL
+    with pytest.raises(agg.AggError) as ex:                         # the plain option is not an engine option
+        r = tts[0]
+        terms, nt, keep = agg.make_tt_terms(r["D"], r["N"], r["tt"])
+        t = ctypes.c_uint64(0)
+        agg.check(agg.lib().agg_submit_tt(eng._h, r["D"], r["N"], terms, nt,
+                                          r["n0"].ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          r["dt"], r["t_end"], agg.AGG_PLAIN | 0, ctypes.byref(t)))
+    assert ex.value.status == agg.AGG_EINVAL
     t_tt = [sub_tt(eng, r) for r in tts]
     t_cp = [eng.submit(r["D"], r["N"], r["kernel"], r["n0"], r["dt"], r["t_end"], prec) for r in cps]
     res = drain(eng, t_tt + t_cp, [r["N"] for r in tts] + [r["N"] for r in cps])
