@@ -94,3 +94,24 @@ def test_noalloc_refuses_beyond_its_array():
     assert L.agg_rhs_noalloc(plan._h, ptr(n), ptr(out), 0) == agg.AGG_EINVAL
     assert L.agg_rhs_noalloc(None, ptr(n), ptr(out), 1) == agg.AGG_EINVAL
     plan.close()
+
+
+def test_noalloc_tensor_train_plan():
+    """A kernel in tensor-train form (random dense cores of ranks (1,3,1),
+    (1,4,4,1), (1,6,6,6,1) at N = 4096: 114 core columns, so the column passes
+    split each group's columns over several workgroups, and the chunked row
+    pass's per-bin chains) through agg_rhs_noalloc: two states, then one, each
+    bit for bit agg_rhs."""
+    rng = np.random.default_rng(95)
+    N = 4096
+    cores = lambda ranks: [rng.uniform(0.1, 1.0, size=(ranks[m], N, ranks[m + 1])) for m in range(len(ranks) - 1)]
+    tt = {2: cores([1, 3, 1]), 3: cores([1, 4, 4, 1]), 4: cores([1, 6, 6, 6, 1])}
+    plan = agg.Plan(4, N, prec="fp64", tt=tt, batch=2)
+    n = torch.tensor(np.concatenate([synth.n0_random_dense(N, 96, decay=2e-3), synth.n0_random_dense(N, 97)]),
+                     dtype=torch.float64, device="cuda:0")
+    for batch in (2, 1):
+        say(f"[noalloc] tensor-train D=4 N={N} fp64 batch {batch}")
+        ref, out = both(plan, n, batch)
+        assert np.array_equal(ref, out), float(np.max(np.abs(ref - out)))
+        assert np.max(np.abs(ref)) > 0
+    plan.close()
